@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""OS-LALM benchmark on one MI355X.
+
+One step = one OS-LALM subset iteration of the whole hot path: x-update
+(regularizer majorizer, continuation rho), forward projection of the next
+subset with fused weighted residual, matched back-projection with the fused
+g-update, regularizer gradient and FP64 restart indicator, and the
+continuation decision.  The workload is the 512^2 fan-beam problem
+(984 views x 888 bins, M = 24 subsets, 40-ellipse seeded phantom, Poisson
+counts at I0 = 5e4); all inputs are resident in GPU memory before timing.
+
+Printed: one JSON line with the throughput (subset iterations / s), the
+roofline figure of the dominant kernel (algorithmic bytes / measured kernel
+time against the 8 TB/s HBM peak) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = {"project": "paper_1402_4381_amd/csrc/project.hip",
+                  "backproject": "paper_1402_4381_amd/csrc/backproject.hip"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(rel):
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, or None
+    when none exists or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256_16") != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg, data, beta, delta, budget_s):
+    """The FP64 oracle's OS-LALM timed on a bounded number of subset steps
+    (its D_L is computed once beforehand, outside the timing, as the GPU's is)."""
+    import oracle as ora
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    DL = ora.sqs_denom(cfg, data["w"])
+    t0 = time.perf_counter()
+    ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=cfg["M"], n_steps=3, denom=DL)
+    per = (time.perf_counter() - t0) / 3.0
+    n = max(3, int(budget_s / max(per, 1e-4)))
+    t0 = time.perf_counter()
+    ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=cfg["M"], n_steps=n, denom=DL)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n / dt, 3), unit="subset_iters/s", cores=threads, kind="oracle",
+                sample="%d OS-LALM subset steps of %s (M=%d, from x0 = 0, incl. the initial "
+                       "subset gradient) with the FP64 oracle: %.1f s" % (n, cfg["name"], cfg["M"], dt))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=960, help="timed subset steps (40 iterations x 24)")
+    ap.add_argument("--warmup", type=int, default=48)
+    ap.add_argument("--workload", default="fan2d_512")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU: the multi-GPU path is not built (see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_1402_4381_amd import lalm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = "cuda:0"
+    cfg = synth.get_config(args.workload)
+    M = cfg["M"]
+    log("bench: generating %s inputs" % args.workload)
+    data = synth.make_problem_data(cfg)
+    plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    y = torch.as_tensor(data["y"][plan.view_of_slot], dtype=torch.float32, device=dev).reshape(-1).contiguous()
+    w = torch.as_tensor(data["w"][plan.view_of_slot], dtype=torch.float32, device=dev).reshape(-1).contiguous()
+    denom = torch.empty(plan.image_elems, device=dev)
+    lalm.lalm_sqs_denom(plan, w, denom)
+    beta = cfg["beta"]
+    delta = synth.configs.delta_mu(cfg)
+    state = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+
+    log("bench: warmup %d steps" % args.warmup)
+    lalm.lalm_iterate(plan, y, w, denom, beta, delta, state, args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: K subset steps, no instrumentation
+    log("bench: timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lalm.lalm_iterate(plan, y, w, denom, beta, delta, state, args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps / dt
+
+    # per-kernel HIP events over a second pass of the same K steps
+    log("bench: kernel timing pass")
+    lalm.lalm_profile_begin(plan)
+    step0 = state.step
+    t1 = time.perf_counter()
+    lalm.lalm_iterate(plan, y, w, denom, beta, delta, state, args.steps)
+    dt_prof = time.perf_counter() - t1
+    ms, cnt = lalm.lalm_profile_read(plan)
+    lalm.lalm_profile_end(plan)
+    avg_ms = ms / np.maximum(cnt, 1)
+
+    # algorithmic bytes per launch, averaged over the subsets the steps visit
+    taps = 4 if cfg["kind"] != 0 else 2
+    nvox = plan.image_elems
+    fp_b = bp_b = 0.0
+    for j in range(step0, step0 + args.steps):
+        m = int(plan.order[(j + 1) % M])
+        s = float(plan.subset_samples[m])
+        rays = float(plan.subset_rays(m))
+        fp_b += s * taps * 4 + rays * 12          # taps + y, w read + residual write
+        bp_b += s * taps * 4 + rays * 4 + nvox * 24   # taps + residual + G, g, x read; G, g, grad R write
+    fp_b /= args.steps
+    bp_b /= args.steps
+    upd_b = nvox * 32.0
+    kern = {"update": (avg_ms[0], upd_b), "project": (avg_ms[1], fp_b), "backproject": (avg_ms[2], bp_b)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    t_ms, b = kern[dom]
+    achieved = b / (t_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(dom, args.workload) if dom in KERNEL_SOURCES else None
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom,
+                    kernel_avg_us=round(t_ms * 1e3, 3),
+                    kernels_avg_us={k: round(v[0] * 1e3, 3) for k, v in kern.items()},
+                    kernels_gbs={k: round(v[1] / (v[0] * 1e-3) / 1e9, 1) for k, v in kern.items()},
+                    bytes_per_launch=int(b))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(cfg, data, beta, delta, args.cpu_seconds)
+
+    out = {
+        "metric": "OS-LALM subset iters/sec",
+        "value": round(value, 2),
+        "unit": "subset_iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "image": [cfg["nz"], cfg["ny"], cfg["nx"]],
+                   "views": cfg["n_views"], "bins": cfg["n_bins"], "rows": cfg["n_rows"],
+                   "subsets": M, "continuation": True, "inner_iters": 1},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "profiled_pass_ms_per_step": round(dt_prof / args.steps * 1e3, 5),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

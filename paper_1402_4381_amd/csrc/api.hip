@@ -1,0 +1,266 @@
+// C ABI entry points: projections, SQS denominator, the OS-LALM iteration
+// and the FP64 monitors.  Argument validation happens before any work is
+// queued; launch failures map to LALM_E_HIP with the HIP error text.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "lalm_internal.h"
+
+using namespace lalm;
+
+namespace {
+
+lalm_status fail(lalm_status code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+lalm_status hip_fail(const char *where, hipError_t e)
+{
+    return fail(LALM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(where, expr)                                  \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(where, e_);    \
+    } while (0)
+
+int64_t subset_slot0(const lalm_plan *p, int m) { return p->slot_offset[m]; }
+
+// Event pairs around the kernels of lalm_iterate when profiling is on.
+struct ProfScope {
+    lalm_plan *p;
+    hipStream_t st;
+    int kind;
+    hipEvent_t stop = nullptr;
+    ProfScope(lalm_plan *p_, int kind_, hipStream_t st_) : p(p_), st(st_), kind(kind_)
+    {
+        if (!p->prof) return;
+        if (p->prof_used + 2 > p->prof_ev.size()) {
+            size_t n = p->prof_ev.size();
+            p->prof_ev.resize(std::max<size_t>(64, 2 * n));
+            for (size_t i = n; i < p->prof_ev.size(); ++i) (void)hipEventCreate(&p->prof_ev[i]);
+        }
+        hipEvent_t start = p->prof_ev[p->prof_used];
+        stop = p->prof_ev[p->prof_used + 1];
+        p->prof_used += 2;
+        p->prof_kind.push_back(kind);
+        (void)hipEventRecord(start, st);
+    }
+    ~ProfScope()
+    {
+        if (stop) (void)hipEventRecord(stop, st);
+    }
+};
+
+// After a stream synchronization: fold recorded pairs into the totals.
+void prof_collect(lalm_plan *p)
+{
+    if (!p->prof) return;
+    for (size_t k = 0; k < p->prof_kind.size(); ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p->prof_ev[2 * k], p->prof_ev[2 * k + 1]) == hipSuccess) {
+            p->prof_ms[p->prof_kind[k]] += ms;
+            p->prof_n[p->prof_kind[k]] += 1;
+        }
+    }
+    p->prof_kind.clear();
+    p->prof_used = 0;
+}
+int subset_nview(const lalm_plan *p, int m) { return (int)(p->slot_offset[m + 1] - p->slot_offset[m]); }
+int64_t subset_ray0(const lalm_plan *p, int m) { return p->slot_offset[m] * p->rays_per_view; }
+
+}  // namespace
+
+extern "C" lalm_status lalm_project_subset(lalm_plan *p, int32_t m, const float *x, float *out_sub,
+                                           const float *y_sub, const float *w_sub, hipStream_t st)
+{
+    if (!p || !x || !out_sub) return fail(LALM_E_INVALID, "lalm_project_subset: null argument");
+    if (m < 0 || m >= p->M) return fail(LALM_E_INVALID, "lalm_project_subset: subset out of range");
+    HIPCHK("project layout", launch_update(p, UPD_LAYOUT, const_cast<float *>(x), nullptr, nullptr,
+                                           nullptr, 0.0f, 0, st));
+    HIPCHK("project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), y_sub, w_sub, out_sub, 0, 0,
+                                nullptr, 0, st));
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_backproject_subset(lalm_plan *p, int32_t m, const float *r_sub, float *x_out,
+                                               float scale, int32_t accumulate, hipStream_t st)
+{
+    if (!p || !r_sub || !x_out) return fail(LALM_E_INVALID, "lalm_backproject_subset: null argument");
+    if (m < 0 || m >= p->M) return fail(LALM_E_INVALID, "lalm_backproject_subset: subset out of range");
+    BpEpi e{};
+    e.scale = scale;
+    e.accumulate = accumulate ? 1 : 0;
+    e.out = x_out;
+    HIPCHK("backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), r_sub, BP_PLAIN, e, st));
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_sqs_denom(lalm_plan *p, const float *w_full, float *denom, hipStream_t st)
+{
+    if (!p || !w_full || !denom) return fail(LALM_E_INVALID, "lalm_sqs_denom: null argument");
+    HIPCHK("sqs ones", launch_update(p, UPD_ONES, nullptr, nullptr, nullptr, nullptr, 0.0f, 0, st));
+    for (int m = 0; m < p->M; ++m) {
+        HIPCHK("sqs project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), nullptr,
+                                        w_full + subset_ray0(p, m), p->d_r, 0, 0, nullptr, 0, st));
+        BpEpi e{};
+        e.scale = 1.0f;
+        e.accumulate = m > 0;
+        e.out = denom;
+        HIPCHK("sqs backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r, BP_PLAIN, e, st));
+    }
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm_state *s,
+                                    int64_t n_steps, const lalm_options *opt, const lalm_stats *stats,
+                                    hipStream_t st)
+{
+    if (!p || !prob || !s || !opt) return fail(LALM_E_INVALID, "lalm_iterate: null argument");
+    if (!prob->y || !prob->w || !prob->denom) return fail(LALM_E_INVALID, "lalm_iterate: null problem array");
+    if (!s->x || !s->g || !s->grad) return fail(LALM_E_INVALID, "lalm_iterate: null state array");
+    if (opt->n_inner != 1) return fail(LALM_E_INVALID, "lalm_iterate: only n_inner = 1 is implemented");
+    if (n_steps < 0) return fail(LALM_E_INVALID, "lalm_iterate: negative step count");
+    if (!(prob->beta >= 0.0) || !(prob->delta > 0.0)) return fail(LALM_E_INVALID, "lalm_iterate: need beta >= 0, delta > 0");
+    if (!(opt->rho_min > 0.0 && opt->rho_min <= 1.0)) return fail(LALM_E_INVALID, "lalm_iterate: rho_min must lie in (0, 1]");
+    if (!opt->continuation && !(opt->rho_fixed > 0.0)) return fail(LALM_E_INVALID, "lalm_iterate: rho_fixed must be positive");
+    if (s->step < 0) return fail(LALM_E_STATE, "lalm_iterate: negative state step");
+    if (s->step > 0 && (s->l < 0 || !(s->rho > 0.0) || !std::isfinite(s->rho)))
+        return fail(LALM_E_STATE, "lalm_iterate: inconsistent continuation state");
+
+    const int M = p->M;
+    const float beta = (float)prob->beta;
+    const float dl = (float)prob->delta;
+    const float inv_delta2 = 1.0f / (dl * dl);
+    BpEpi e{};
+    e.scale = (float)M;
+    e.G = s->grad;
+    e.g = s->g;
+    e.x = s->x;
+    e.beta = beta;
+    e.inv_delta2 = inv_delta2;
+    e.cont.continuation = opt->continuation ? 1 : 0;
+    e.cont.rho_fixed = opt->rho_fixed;
+    e.cont.rho_min = opt->rho_min;
+    e.cont.forced = opt->forced_restart;
+    e.cont.forced_len = opt->forced_restart ? opt->forced_len : 0;
+    if (stats) {
+        e.cont.st_rho = stats->rho;
+        e.cont.st_xi = stats->xi;
+        e.cont.st_restart = stats->restart;
+        e.cont.st_cap = stats->capacity;
+    }
+
+    if (s->step == 0) {
+        HIPCHK("iterate scalars", launch_set_scalars(p, 0, opt->continuation ? 1.0 : opt->rho_fixed, 0, st));
+        HIPCHK("iterate layout", launch_update(p, UPD_LAYOUT, s->x, nullptr, nullptr, nullptr, 0.0f, 0, st));
+        const int m0 = p->order[0];
+        HIPCHK("iterate init project", launch_fp(p, subset_slot0(p, m0), subset_nview(p, m0),
+                                                 prob->y + subset_ray0(p, m0), prob->w + subset_ray0(p, m0),
+                                                 p->d_r, 0, 0, nullptr, 1, st));
+        HIPCHK("iterate init backproject", launch_bp(p, subset_slot0(p, m0), subset_nview(p, m0), p->d_r,
+                                                     BP_INIT, e, st));
+    } else {
+        const double rho = opt->continuation ? s->rho : opt->rho_fixed;
+        HIPCHK("iterate scalars", launch_set_scalars(p, s->l, rho, s->step, st));
+        HIPCHK("iterate resume", launch_reg_grad(p, s->x, beta, inv_delta2, st));
+    }
+    for (int64_t t = 0; t < n_steps; ++t) {
+        const int64_t j = s->step + t;
+        const int m = p->order[(size_t)((j + 1) % M)];
+        {
+            ProfScope ps(p, 0, st);
+            HIPCHK("iterate update", launch_update(p, UPD_STEP, s->x, s->grad, s->g, prob->denom, beta,
+                                                   prob->nonneg, st));
+        }
+        {
+            ProfScope ps(p, 1, st);
+            HIPCHK("iterate project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m),
+                                                prob->y + subset_ray0(p, m), prob->w + subset_ray0(p, m),
+                                                p->d_r, 0, 0, nullptr, 1, st));
+        }
+        {
+            ProfScope ps(p, 2, st);
+            HIPCHK("iterate backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r,
+                                                    BP_STEP, e, st));
+        }
+    }
+    HIPCHK("iterate readback", hipMemcpyAsync(p->h_sc, p->d_sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK("iterate sync", hipStreamSynchronize(st));
+    prof_collect(p);
+    s->step = p->h_sc->step;
+    s->l = p->h_sc->l;
+    s->rho = p->h_sc->rho;
+    if (p->h_sc->status)
+        return fail(LALM_E_NONFINITE, "lalm_iterate: non-finite restart indicator; later steps skipped");
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_cost_f64(lalm_plan *p, const lalm_problem *prob, const float *x,
+                                     double *out_dev, hipStream_t st)
+{
+    if (!p || !prob || !x || !out_dev || !prob->y || !prob->w)
+        return fail(LALM_E_INVALID, "lalm_cost_f64: null argument");
+    if (!(prob->delta > 0.0)) return fail(LALM_E_INVALID, "lalm_cost_f64: need delta > 0");
+    HIPCHK("cost layout", launch_update(p, UPD_LAYOUT, const_cast<float *>(x), nullptr, nullptr, nullptr,
+                                        0.0f, 0, st));
+    for (int m = 0; m < p->M; ++m) {
+        int64_t nblk = 0;
+        HIPCHK("cost project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), prob->y + subset_ray0(p, m),
+                                         prob->w + subset_ray0(p, m), nullptr, 1, 0, &nblk, 0, st));
+        HIPCHK("cost sum", launch_sum_partials(p->d_partials, nblk, p->d_tmp + 8 + m, 1.0, st));
+    }
+    HIPCHK("cost data", launch_sum_partials(p->d_tmp + 8, p->M, p->d_tmp + 0, 1.0, st));
+    HIPCHK("cost reg", launch_reg_value(p, x, prob->beta, prob->delta, p->d_tmp + 1, st));
+    HIPCHK("cost combine", launch_combine_cost(out_dev, p->d_tmp + 0, p->d_tmp + 1, st));
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_dot_f64(lalm_plan *p, const float *a, const float *b, int64_t n,
+                                    double *out_dev, hipStream_t st)
+{
+    if (!p || !a || !b || !out_dev || n < 0) return fail(LALM_E_INVALID, "lalm_dot_f64: bad argument");
+    HIPCHK("dot", launch_dot(p, a, b, n, out_dev, st));
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_roi_rmsd_f64(lalm_plan *p, const float *a, const float *b, double radius_mm,
+                                         double *out_dev, hipStream_t st)
+{
+    if (!p || !a || !b || !out_dev || !(radius_mm >= 0.0))
+        return fail(LALM_E_INVALID, "lalm_roi_rmsd_f64: bad argument");
+    HIPCHK("rmsd", launch_rmsd(p, a, b, radius_mm, out_dev, st));
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_profile_begin(lalm_plan *p)
+{
+    if (!p) return fail(LALM_E_INVALID, "lalm_profile_begin: null plan");
+    p->prof = true;
+    p->prof_kind.clear();
+    p->prof_used = 0;
+    for (int k = 0; k < 3; ++k) { p->prof_ms[k] = 0.0; p->prof_n[k] = 0; }
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_profile_read(lalm_plan *p, double *ms, int64_t *counts)
+{
+    if (!p || !ms || !counts) return fail(LALM_E_INVALID, "lalm_profile_read: null argument");
+    for (int k = 0; k < 3; ++k) { ms[k] = p->prof_ms[k]; counts[k] = p->prof_n[k]; }
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_profile_end(lalm_plan *p)
+{
+    if (!p) return fail(LALM_E_INVALID, "lalm_profile_end: null plan");
+    p->prof = false;
+    for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+    p->prof_ev.clear();
+    p->prof_kind.clear();
+    p->prof_used = 0;
+    return LALM_OK;
+}

@@ -1,0 +1,166 @@
+// Internal declarations of the gfx950 OS-LALM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lalm.h"
+
+namespace lalm {
+
+// ---------------------------------------------------------------- tables
+//
+// Per (sinogram slot, bin) Joseph parameters, computed in FP64 on the host
+// and stored as FP32.  For slice s of the dominant in-plane axis the sample
+// sits at fractional index eta(s) = a + s*c along the other in-plane axis;
+// sc is the in-plane ray length per slice.  meta packs the dominant axis
+// (bit 31: 0 = x, 1 = y) and the conservative slice range [s_lo, s_hi]
+// (bits 0..15 and 16..30) outside of which no tap can fall inside the image.
+struct RayRec {
+    float a, c, sc;
+    uint32_t meta;
+};
+// 3D only: q(s) = m + s*k; the slice coordinate of the sample is
+// zeta = z0(view) + v_r * q(s).
+struct RayRecZ {
+    float m, k;
+};
+// Per slot: source position (mm, relative to the isocentre), cos/sin of the
+// view angle, and z0 = (S_z - Z_0) / dz.
+struct ViewRec {
+    float sx, sy, cb, sb;
+    float z0, pad0, pad1, pad2;
+};
+
+constexpr uint32_t kYDom = 0x80000000u;
+__host__ __device__ inline int meta_lo(uint32_t m) { return int(m & 0xFFFFu); }
+__host__ __device__ inline int meta_hi(uint32_t m) { return int((m >> 16) & 0x7FFFu); }
+__host__ __device__ inline bool meta_ydom(uint32_t m) { return (m & kYDom) != 0; }
+
+// Scalars that live on the device across the steps of lalm_iterate.
+struct DevScalars {
+    double rho;       // rho used by the next step
+    double xi;        // last restart indicator
+    long long l;      // continuation counter
+    long long step;   // global subset-step counter
+    int status;       // 0 ok, 1 non-finite restart indicator met
+    int pad;
+};
+
+// Geometry constants handed to kernels by value.
+struct GeoK {
+    int nx, ny, nz, nb, nr;
+    int is3d;
+    float dx, dy, dz;
+    float x0, y0;             // centre of voxel (0, 0) in mm
+    float dsd_over_ds;        // bins per radian of fan angle
+    float bin_center;         // (nb-1)/2 + channel offset
+    float dmax;               // max(dx, dy)
+    float inv_dt;             // 1 / dt
+    float row_center;         // (nr-1)/2
+    // padded image copies
+    int ldT, ldN;             // padded length of the fastest axis: ny+4, nx+4
+    long long slabT, slabN;   // elements per slice of the dominant axis
+};
+
+// Continuation bookkeeping handed to the back-projection epilogue.
+struct ContArgs {
+    int continuation;
+    double rho_fixed, rho_min;
+    const uint8_t *forced;
+    long long forced_len;
+    double *st_rho, *st_xi;
+    uint8_t *st_restart;
+    long long st_cap;
+};
+
+}  // namespace lalm
+
+struct lalm_plan {
+    lalm_geometry g;
+    int M = 0;
+    int nx = 0, ny = 0, nz = 0, nb = 0, nr = 0, nv = 0;
+    bool is3d = false;
+    int device = 0;
+    std::vector<int32_t> order;
+    std::vector<int32_t> view_of_slot;
+    std::vector<int64_t> slot_offset;   // [M+1] first slot of each subset
+    std::vector<int64_t> subset_samples;
+    int64_t rays_per_view = 0;
+    int64_t max_subset_rays = 0;
+    lalm::GeoK k{};
+    // device memory owned by the plan
+    lalm::RayRec *d_rays = nullptr;     // [n_views][nb] in slot order
+    lalm::RayRecZ *d_raysz = nullptr;   // [n_views][nb] (3D)
+    lalm::ViewRec *d_views = nullptr;   // [n_views] in slot order
+    float *d_rowv = nullptr;            // [nr] v_r (mm)
+    float *d_rowf = nullptr;            // [nr] sqrt(1 + (v_r/dsd)^2)
+    float *d_xt = nullptr;              // padded copy for x-dominant rays
+    float *d_xn = nullptr;              // padded copy for y-dominant rays
+    float *d_gradR = nullptr;           // regularizer gradient image
+    float *d_r = nullptr;               // subset residual
+    double *d_partials = nullptr;       // reduction partials
+    int64_t n_partials = 0;
+    unsigned int *d_counter = nullptr;  // last-block counter
+    lalm::DevScalars *d_sc = nullptr;
+    lalm::DevScalars *h_sc = nullptr;   // pinned host mirror
+    double *d_tmp = nullptr;            // small FP64 scratch (monitors)
+    int fp_nseg = 1;
+    // optional per-kernel event timing
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;     // pool: pairs (start, stop)
+    std::vector<int> prof_kind;          // kernel class of each recorded pair
+    size_t prof_used = 0;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_n[3] = {0, 0, 0};
+};
+
+namespace lalm {
+
+void set_error(const std::string &msg);
+
+// Launchers (defined in the .hip files).  All return hipError_t of the launch.
+// Forward projection of the subset starting at slot `slot0` holding `nview`
+// views.  mode 0: out = w .* (A x - y) (y, w may be null);
+// mode 1: accumulate 1/2 sum w (A x - y)^2 into partials[part_off + block].
+hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *y,
+                     const float *w, float *out, int mode, int64_t part_off,
+                     int64_t *n_blocks_out, int check_status, hipStream_t st);
+
+enum BpMode { BP_PLAIN = 0, BP_INIT = 1, BP_STEP = 2 };
+struct BpEpi {
+    float scale;           // PLAIN: scale; INIT/STEP: M
+    int accumulate;        // PLAIN
+    float *out;            // PLAIN: output image
+    float *G, *g;          // INIT/STEP
+    const float *x;        // INIT/STEP: image for grad R
+    float beta, inv_delta2;   // regularizer: beta, 1/delta^2
+    ContArgs cont;
+};
+hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *r, int mode,
+                     const BpEpi &e, hipStream_t st);
+
+enum UpdMode { UPD_LAYOUT = 0, UPD_ONES = 1, UPD_STEP = 2 };
+hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
+                         const float *denom, float beta, int nonneg, hipStream_t st);
+hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,
+                           hipStream_t st);
+hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,
+                              hipStream_t st);
+
+// FP64 reductions
+hipError_t launch_sum_partials(const double *part, int64_t n, double *out, double scale,
+                               hipStream_t st);
+hipError_t launch_dot(const lalm_plan *p, const float *a, const float *b, int64_t n,
+                      double *out, hipStream_t st);
+hipError_t launch_reg_value(const lalm_plan *p, const float *x, double beta, double delta,
+                            double *out, hipStream_t st);
+hipError_t launch_rmsd(const lalm_plan *p, const float *a, const float *b, double radius,
+                       double *out, hipStream_t st);
+hipError_t launch_combine_cost(double *out3, const double *data, const double *reg,
+                               hipStream_t st);
+
+}  // namespace lalm

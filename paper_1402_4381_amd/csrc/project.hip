@@ -1,0 +1,303 @@
+// Forward projection (ray-driven Joseph) and the image-layout / x-update
+// kernel that feeds it.
+//
+// Data layout.  The projector never reads the caller's [z][y][x] image.  It
+// reads two zero-padded copies that the x-update kernel writes as a side
+// product of every update:
+//   XT[i][k+2][j+2]  (x-dominant rays: y fastest)   size nx * (nz+4) * (ny+4)
+//   XN[j][k+2][i+2]  (y-dominant rays: x fastest)   size ny * (nz+4) * (nx+4)
+// (2D: no z padding).  A wavefront holds 64 adjacent detector channels of one
+// view and row; at a given slice their interpolation positions are adjacent,
+// so each tap load touches a few contiguous cache lines.  The two-voxel zero
+// border on every interpolated axis lets the inner loop clamp indices instead
+// of testing bounds: a clamped out-of-range tap always reads a zero.
+#include "lalm_internal.h"
+
+namespace lalm {
+namespace {
+
+struct FPArgs {
+    GeoK k;
+    const RayRec *rays;     // subset's rays, [view][bin]
+    const RayRecZ *raysz;   // 3D
+    const ViewRec *views;   // subset's views
+    const float *rowv, *rowf;
+    const float *XT, *XN;
+    long long nrays;
+    const float *y, *w;
+    float *out;
+    double *partials;       // mode 1
+    const int *status;      // skip when set (LALM steps only)
+};
+
+template <bool IS3D, int NSEG, int MODE>
+__global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
+{
+    const GeoK &K = A.k;
+    const int lane = threadIdx.x, seg = threadIdx.y;
+    if (A.status && *A.status) return;
+    const long long q = (long long)blockIdx.x * 64 + lane;
+    const bool valid = q < A.nrays;
+    float acc = 0.0f;
+    RayRec rr{0.f, 0.f, 0.f, 1u};
+    int r = 0;
+    if (valid) {
+        const int b = (int)(q % K.nb);
+        const long long vrow = q / K.nb;
+        r = IS3D ? (int)(vrow % K.nr) : 0;
+        const int kv = IS3D ? (int)(vrow / K.nr) : (int)vrow;
+        rr = A.rays[(long long)kv * K.nb + b];
+        const bool ydom = meta_ydom(rr.meta);
+        const int ns = ydom ? K.ny : K.nx;
+        const int seglen = (ns + NSEG - 1) / NSEG;
+        int s0 = max(meta_lo(rr.meta), seg * seglen);
+        int s1 = min(meta_hi(rr.meta), seg * seglen + seglen - 1);
+        const float *img = ydom ? A.XN : A.XT;
+        const int lim = ydom ? K.nx : K.ny;
+        if (!IS3D) {
+            const int ld = ydom ? K.ldN : K.ldT;
+            const float *base = img + 2;
+            for (int s = s0; s <= s1; ++s) {
+                const float eta = fmaf((float)s, rr.c, rr.a);
+                const float fl = floorf(eta);
+                const float f = eta - fl;
+                const int j0 = min(max((int)fl, -2), lim);
+                const float *pp = base + (long long)s * ld + j0;
+                const float v0 = pp[0], v1 = pp[1];
+                acc += fmaf(f, v1 - v0, v0);
+            }
+        } else {
+            const RayRecZ rz = A.raysz[(long long)kv * K.nb + b];
+            const float z0 = A.views[kv].z0;
+            const float vr = A.rowv[r];
+            // restrict to the slices where zeta = z0 + vr*(m + s*k) lies in
+            // [-1, nz); one slice of margin covers FP32 rounding
+            const float slope = vr * rz.k, off = fmaf(vr, rz.m, z0);
+            if (slope != 0.0f) {
+                float ta = (-1.0f - off) / slope, tb = ((float)K.nz - off) / slope;
+                float lo = fminf(ta, tb), hi = fmaxf(ta, tb);
+                lo = fmaxf(lo, -4.0f);
+                hi = fminf(hi, (float)(ns + 4));
+                s0 = max(s0, (int)floorf(lo) - 1);
+                s1 = min(s1, (int)ceilf(hi) + 1);
+            } else if (!(off >= -1.0f && off < (float)K.nz)) {
+                s1 = s0 - 1;
+            }
+            const int ld = ydom ? K.ldN : K.ldT;
+            const long long slab = ydom ? K.slabN : K.slabT;
+            const float *base = img + 2 * ld + 2;
+            for (int s = s0; s <= s1; ++s) {
+                const float eta = fmaf((float)s, rr.c, rr.a);
+                const float qz = fmaf((float)s, rz.k, rz.m);
+                const float zeta = fmaf(vr, qz, z0);
+                const float fl = floorf(eta), zl = floorf(zeta);
+                const float f = eta - fl, h = zeta - zl;
+                const int j0 = min(max((int)fl, -2), lim);
+                const int k0 = min(max((int)zl, -2), K.nz);
+                const float *pp = base + (long long)s * slab + (long long)k0 * ld + j0;
+                const float v00 = pp[0], v01 = pp[1], v10 = pp[ld], v11 = pp[ld + 1];
+                const float lo = fmaf(f, v01 - v00, v00);
+                const float up = fmaf(f, v11 - v10, v10);
+                acc += fmaf(h, up - lo, lo);
+            }
+        }
+    }
+    if (NSEG > 1) {
+        __shared__ float red[NSEG][64];
+        red[seg][lane] = acc;
+        __syncthreads();
+        if (seg != 0) return;
+        acc = red[0][lane];
+#pragma unroll
+        for (int t = 1; t < NSEG; ++t) acc += red[t][lane];
+    }
+    float val = 0.0f, wv = 0.0f;
+    if (valid) {
+        const float proj = acc * rr.sc * (IS3D ? A.rowf[r] : 1.0f);
+        const float yv = A.y ? A.y[q] : 0.0f;
+        wv = A.w ? A.w[q] : 1.0f;
+        val = proj - yv;
+        if (MODE == 0) A.out[q] = wv * val;
+    }
+    if (MODE == 1) {
+        // 1/2 w e^2 summed in FP64 over the block's rays (one wavefront)
+        double t = valid ? 0.5 * (double)wv * (double)val * (double)val : 0.0;
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0) A.partials[blockIdx.x] = t;
+    }
+}
+
+template <bool IS3D, int NSEG>
+hipError_t fp_dispatch_mode(const FPArgs &a, int mode, long long nblk, hipStream_t st)
+{
+    dim3 blk(64, NSEG), grd((unsigned)nblk);
+    if (mode == 0) hipLaunchKernelGGL((fp_kernel<IS3D, NSEG, 0>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((fp_kernel<IS3D, NSEG, 1>), grd, blk, 0, st, a);
+    return hipGetLastError();
+}
+
+template <bool IS3D>
+hipError_t fp_dispatch(const FPArgs &a, int nseg, int mode, long long nblk, hipStream_t st)
+{
+    switch (nseg) {
+    case 1: return fp_dispatch_mode<IS3D, 1>(a, mode, nblk, st);
+    case 2: return fp_dispatch_mode<IS3D, 2>(a, mode, nblk, st);
+    case 4: return fp_dispatch_mode<IS3D, 4>(a, mode, nblk, st);
+    default: return fp_dispatch_mode<IS3D, 8>(a, mode, nblk, st);
+    }
+}
+
+// ---------------------------------------------------------------- x-update
+//
+// One thread per voxel of a 32x32 (x, y) tile of one z slice.  Writes the
+// caller's image (UPD_STEP), XN directly (x fastest) and XT through an LDS
+// transpose (y fastest), so every global store is coalesced.
+struct UpdArgs {
+    GeoK k;
+    float *x;
+    const float *G, *g, *gradR, *denom;
+    float *XT, *XN;
+    const DevScalars *sc;
+    float beta;
+    int nonneg;
+};
+
+// Number-weighted neighbour sum 2 * sum_{k in N(j)} kappa_jk for voxel (i,j,k)
+// (the separable majorizer curvature of the hyperbola regularizer over beta).
+__device__ inline float reg_curv_sum(const GeoK &K, int i, int j, int k)
+{
+    const float r2 = 0.70710678118654752f, r3 = 0.57735026918962576f;
+    int cx = (i > 0) + (i < K.nx - 1);
+    int cy = (j > 0) + (j < K.ny - 1);
+    int cz = K.is3d ? (k > 0) + (k < K.nz - 1) : 0;
+    // neighbours along 1, 2 or 3 axes: counts are products of per-axis counts
+    float s1 = (float)(cx + cy + cz);
+    float s2 = (float)(cx * cy + cx * cz + cy * cz);
+    float s3 = (float)(cx * cy * cz);
+    return 2.0f * (s1 + s2 * r2 + s3 * r3);
+}
+
+template <bool IS3D, int MODE>
+__global__ void __launch_bounds__(256) update_kernel(UpdArgs A)
+{
+    const GeoK &K = A.k;
+    if (MODE == UPD_STEP && A.sc->status) return;
+    __shared__ float tile[32][33];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int k = blockIdx.z;
+    float rho = 1.0f;
+    if (MODE == UPD_STEP) rho = (float)A.sc->rho;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty + 8 * qq;
+        float v = 0.0f;
+        if (i < K.nx && j < K.ny) {
+            const long long idx = ((long long)k * K.ny + j) * K.nx + i;
+            if (MODE == UPD_ONES) {
+                v = 1.0f;
+            } else {
+                v = A.x[idx];
+                if (MODE == UPD_STEP) {
+                    const float num = fmaf(rho, A.G[idx], (1.0f - rho) * A.g[idx]) + A.gradR[idx];
+                    const float den = fmaf(rho, A.denom[idx], A.beta * reg_curv_sum(K, i, j, k));
+                    if (den > 0.0f) {
+                        v = v - num / den;
+                        if (A.nonneg) v = fmaxf(v, 0.0f);
+                    }
+                    A.x[idx] = v;
+                }
+            }
+            const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
+                                         : ((long long)j * K.ldN + i + 2);
+            A.XN[n_idx] = v;
+        }
+        tile[ty + 8 * qq][tx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const int i = blockIdx.x * 32 + ty + 8 * qq, j = blockIdx.y * 32 + tx;
+        if (i < K.nx && j < K.ny) {
+            const long long t_idx = IS3D ? ((long long)i * K.slabT + (long long)(k + 2) * K.ldT + j + 2)
+                                         : ((long long)i * K.ldT + j + 2);
+            A.XT[t_idx] = tile[tx][ty + 8 * qq];
+        }
+    }
+}
+
+template <bool IS3D>
+hipError_t upd_dispatch(const UpdArgs &a, int mode, hipStream_t st)
+{
+    dim3 blk(32, 8), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, a.k.nz);
+    if (mode == UPD_LAYOUT) hipLaunchKernelGGL((update_kernel<IS3D, UPD_LAYOUT>), grd, blk, 0, st, a);
+    else if (mode == UPD_ONES) hipLaunchKernelGGL((update_kernel<IS3D, UPD_ONES>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((update_kernel<IS3D, UPD_STEP>), grd, blk, 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long long step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->rho = rho;
+        sc->xi = 0.0;
+        sc->l = l;
+        sc->step = step;
+        sc->status = 0;
+        sc->pad = 0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
+                     float *out, int mode, int64_t part_off, int64_t *n_blocks_out,
+                     int check_status, hipStream_t st)
+{
+    FPArgs a;
+    a.k = p->k;
+    a.rays = p->d_rays + slot0 * p->nb;
+    a.raysz = p->is3d ? p->d_raysz + slot0 * p->nb : nullptr;
+    a.views = p->d_views + slot0;
+    a.rowv = p->d_rowv;
+    a.rowf = p->d_rowf;
+    a.XT = p->d_xt;
+    a.XN = p->d_xn;
+    a.nrays = (long long)nview * p->rays_per_view;
+    a.y = y;
+    a.w = w;
+    a.out = out;
+    a.partials = p->d_partials + part_off;
+    a.status = check_status ? &p->d_sc->status : nullptr;
+    long long nblk = (a.nrays + 63) / 64;
+    if (n_blocks_out) *n_blocks_out = nblk;
+    if (nblk == 0) return hipSuccess;
+    return p->is3d ? fp_dispatch<true>(a, p->fp_nseg, mode, nblk, st)
+                   : fp_dispatch<false>(a, p->fp_nseg, mode, nblk, st);
+}
+
+hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
+                         const float *denom, float beta, int nonneg, hipStream_t st)
+{
+    UpdArgs a;
+    a.k = p->k;
+    a.x = x;
+    a.G = G;
+    a.g = g;
+    a.gradR = p->d_gradR;
+    a.denom = denom;
+    a.XT = p->d_xt;
+    a.XN = p->d_xn;
+    a.sc = p->d_sc;
+    a.beta = beta;
+    a.nonneg = nonneg;
+    return p->is3d ? upd_dispatch<true>(a, mode, st) : upd_dispatch<false>(a, mode, st);
+}
+
+hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, p->d_sc, l, rho, step);
+    return hipGetLastError();
+}
+
+}  // namespace lalm

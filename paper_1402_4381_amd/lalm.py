@@ -1,0 +1,328 @@
+"""Python binding of ``liblalm.so`` (argument marshalling only).
+
+Every function here has the name of the C ABI call it wraps (``include/
+lalm.h``) and does nothing but check and pass pointers, sizes and the HIP
+stream; all arithmetic runs in the library's gfx950 kernels.  Device buffers
+are torch tensors on the GPU (float32, contiguous); the stream defaults to
+torch's current stream.  The library must be built first
+(``python -m paper_1402_4381_amd.build``); importing this module without it
+raises ImportError, and there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblalm.so")
+
+LALM_OK, LALM_E_INVALID, LALM_E_HIP, LALM_E_NOMEM, LALM_E_NONFINITE, LALM_E_STATE = 0, -1, -2, -3, -4, -5
+FAN2D, CONE_AXIAL, CONE_HELICAL = 0, 1, 2
+
+EXPORTS = ("lalm_last_error", "lalm_version", "lalm_plan_geometry", "lalm_plan_info",
+           "lalm_plan_destroy", "lalm_project_subset", "lalm_backproject_subset",
+           "lalm_sqs_denom", "lalm_iterate", "lalm_cost_f64", "lalm_dot_f64",
+           "lalm_roi_rmsd_f64", "lalm_profile_begin", "lalm_profile_read",
+           "lalm_profile_end")
+
+
+class LalmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("lalm status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("dz", ctypes.c_double), ("n_views", ctypes.c_int32),
+                ("n_views_per_turn", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("n_rows", ctypes.c_int32), ("ds", ctypes.c_double), ("dt", ctypes.c_double),
+                ("dso", ctypes.c_double), ("dsd", ctypes.c_double),
+                ("start_angle", ctypes.c_double), ("pitch", ctypes.c_double),
+                ("channel_offset", ctypes.c_double), ("detector", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_void_p), ("w", ctypes.c_void_p), ("denom", ctypes.c_void_p),
+                ("beta", ctypes.c_double), ("delta", ctypes.c_double), ("nonneg", ctypes.c_int32)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("g", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("step", ctypes.c_int64), ("l", ctypes.c_int64), ("rho", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("continuation", ctypes.c_int32), ("rho_fixed", ctypes.c_double),
+                ("rho_min", ctypes.c_double), ("n_inner", ctypes.c_int32),
+                ("forced_restart", ctypes.c_void_p), ("forced_len", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("restart", ctypes.c_void_p),
+                ("capacity", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblalm.so is not built (python -m paper_1402_4381_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64, F32, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    sig = {
+        "lalm_last_error": ([], ctypes.c_char_p),
+        "lalm_version": ([], ctypes.c_char_p),
+        "lalm_plan_geometry": ([ctypes.POINTER(Geometry), I32, ctypes.POINTER(P)], I32),
+        "lalm_plan_info": ([P, P, P, P, P, P, P], I32),
+        "lalm_plan_destroy": ([P], I32),
+        "lalm_project_subset": ([P, I32, P, P, P, P, P], I32),
+        "lalm_backproject_subset": ([P, I32, P, P, F32, I32, P], I32),
+        "lalm_sqs_denom": ([P, P, P, P], I32),
+        "lalm_iterate": ([P, ctypes.POINTER(Problem), ctypes.POINTER(State), I64,
+                          ctypes.POINTER(Options), ctypes.POINTER(Stats), P], I32),
+        "lalm_cost_f64": ([P, ctypes.POINTER(Problem), P, P, P], I32),
+        "lalm_dot_f64": ([P, P, P, I64, P, P], I32),
+        "lalm_roi_rmsd_f64": ([P, P, P, F64, P, P], I32),
+        "lalm_profile_begin": ([P], I32),
+        "lalm_profile_read": ([P, P, P], I32),
+        "lalm_profile_end": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status):
+    if status != LALM_OK:
+        raise LalmError(status, _lib.lalm_last_error().decode())
+
+
+def _dev(t, name, dtype="float32", numel=None, allow_none=False):
+    """Device address of a contiguous GPU tensor (validated)."""
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError("%s: a tensor is required" % name)
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s: expected a GPU tensor" % name)
+    if str(t.dtype) != "torch." + dtype:
+        raise ValueError("%s: expected %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s: expected a contiguous tensor" % name)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s: needs %d elements, has %d" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def lalm_version():
+    return _lib.lalm_version().decode()
+
+
+def lalm_last_error():
+    return _lib.lalm_last_error().decode()
+
+
+class Plan:
+    """Owner of a ``lalm_plan`` handle and its host-side facts."""
+
+    def __init__(self, handle, geom, n_subsets):
+        self.handle = handle
+        self.geom = dict(geom)
+        self.M = n_subsets
+        n_views = geom["n_views"]
+        img = ctypes.c_int64()
+        sino = ctypes.c_int64()
+        off = np.zeros(n_subsets + 1, dtype=np.int64)
+        order = np.zeros(n_subsets, dtype=np.int32)
+        vos = np.zeros(n_views, dtype=np.int32)
+        samp = np.zeros(n_subsets, dtype=np.int64)
+        _check(_lib.lalm_plan_info(handle, ctypes.byref(img), ctypes.byref(sino),
+                                   off.ctypes.data_as(ctypes.c_void_p),
+                                   order.ctypes.data_as(ctypes.c_void_p),
+                                   vos.ctypes.data_as(ctypes.c_void_p),
+                                   samp.ctypes.data_as(ctypes.c_void_p)))
+        self.image_elems = img.value
+        self.sino_elems = sino.value
+        self.subset_ray_offset = off
+        self.order = order
+        self.view_of_slot = vos
+        self.subset_samples = samp
+        self.image_shape = (geom["nz"], geom["ny"], geom["nx"])
+        self.rays_per_view = geom["n_rows"] * geom["n_bins"]
+
+    def subset_rays(self, m):
+        if not 0 <= m < self.M:
+            return 0          # out-of-range subsets are rejected by the library
+        return int(self.subset_ray_offset[m + 1] - self.subset_ray_offset[m])
+
+    def subset_slice(self, m):
+        return slice(int(self.subset_ray_offset[m]), int(self.subset_ray_offset[m + 1]))
+
+    def subset_views(self, m):
+        a = self.subset_ray_offset[m] // self.rays_per_view
+        b = self.subset_ray_offset[m + 1] // self.rays_per_view
+        return self.view_of_slot[a:b]
+
+    def to_subset_major(self, sino):
+        """Natural-order sinogram ``[n_views, rows, bins]`` -> flat subset-major
+        (a permutation of whole views)."""
+        return sino[self.view_of_slot].reshape(-1)
+
+    def from_subset_major(self, flat):
+        nv = self.geom["n_views"]
+        s = flat.reshape(nv, self.geom["n_rows"], self.geom["n_bins"])
+        out = s.clone() if hasattr(s, "clone") else s.copy()
+        out[self.view_of_slot] = s
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                _lib.lalm_plan_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def _geometry(geom):
+    g = Geometry()
+    for name, _ in Geometry._fields_:
+        setattr(g, name, geom[name])
+    return g
+
+
+def lalm_plan_geometry(geom, n_subsets):
+    """Plan a geometry (a dict with the ``lalm_geometry`` fields)."""
+    h = ctypes.c_void_p()
+    _check(_lib.lalm_plan_geometry(ctypes.byref(_geometry(geom)), int(n_subsets), ctypes.byref(h)))
+    return Plan(h, geom, int(n_subsets))
+
+
+def lalm_plan_info(plan):
+    return dict(image_elems=plan.image_elems, sino_elems=plan.sino_elems,
+                subset_ray_offset=plan.subset_ray_offset.copy(), order=plan.order.copy(),
+                view_of_slot=plan.view_of_slot.copy(), subset_samples=plan.subset_samples.copy())
+
+
+def lalm_plan_destroy(plan):
+    if plan.handle:
+        _check(_lib.lalm_plan_destroy(plan.handle))
+        plan.handle = None
+
+
+def lalm_project_subset(plan, m, x, out, y=None, w=None, stream=None):
+    n = plan.subset_rays(m)
+    _check(_lib.lalm_project_subset(plan.handle, int(m), _dev(x, "x", numel=plan.image_elems),
+                                    _dev(out, "out", numel=n), _dev(y, "y", numel=n, allow_none=True),
+                                    _dev(w, "w", numel=n, allow_none=True), _stream(stream)))
+
+
+def lalm_backproject_subset(plan, m, r, x_out, scale=1.0, accumulate=False, stream=None):
+    _check(_lib.lalm_backproject_subset(plan.handle, int(m), _dev(r, "r", numel=plan.subset_rays(m)),
+                                        _dev(x_out, "x_out", numel=plan.image_elems), float(scale),
+                                        1 if accumulate else 0, _stream(stream)))
+
+
+def lalm_sqs_denom(plan, w_full, denom, stream=None):
+    _check(_lib.lalm_sqs_denom(plan.handle, _dev(w_full, "w_full", numel=plan.sino_elems),
+                               _dev(denom, "denom", numel=plan.image_elems), _stream(stream)))
+
+
+def _problem(plan, y, w, denom, beta, delta, nonneg):
+    return Problem(_dev(y, "y", numel=plan.sino_elems), _dev(w, "w", numel=plan.sino_elems),
+                   _dev(denom, "denom", numel=plan.image_elems) if denom is not None else None,
+                   float(beta), float(delta), 1 if nonneg else 0)
+
+
+class LalmState:
+    """Caller-owned iteration state: GPU images x, g, grad and the scalars."""
+
+    def __init__(self, x, g, grad, step=0, l=0, rho=1.0):
+        self.x, self.g, self.grad = x, g, grad
+        self.step, self.l, self.rho = int(step), int(l), float(rho)
+
+    @classmethod
+    def zeros_like(cls, x):
+        import torch
+        return cls(x, torch.zeros_like(x), torch.zeros_like(x))
+
+    def clone(self):
+        return LalmState(self.x.clone(), self.g.clone(), self.grad.clone(), self.step, self.l, self.rho)
+
+
+def lalm_iterate(plan, y, w, denom, beta, delta, state, n_steps, continuation=True,
+                 rho_fixed=1.0, rho_min=1e-3, n_inner=1, nonneg=True, forced_restart=None,
+                 stats=None, stream=None):
+    """Run ``n_steps`` subset steps; ``state`` (LalmState) is updated in place.
+    ``stats``: optional dict of GPU tensors rho (float64), xi (float64),
+    restart (uint8) indexed by global step.  ``forced_restart``: optional
+    uint8 GPU tensor indexed by global step."""
+    prob = _problem(plan, y, w, denom, beta, delta, nonneg)
+    st = State(_dev(state.x, "x", numel=plan.image_elems), _dev(state.g, "g", numel=plan.image_elems),
+               _dev(state.grad, "grad", numel=plan.image_elems), state.step, state.l, state.rho)
+    fr = _dev(forced_restart, "forced_restart", dtype="uint8", allow_none=True)
+    opt = Options(1 if continuation else 0, float(rho_fixed), float(rho_min), int(n_inner), fr,
+                  int(forced_restart.numel()) if forced_restart is not None else 0)
+    sp = None
+    if stats is not None:
+        cap = min(stats["rho"].numel(), stats["xi"].numel(), stats["restart"].numel())
+        sp = ctypes.byref(Stats(_dev(stats["rho"], "stats.rho", dtype="float64"),
+                                _dev(stats["xi"], "stats.xi", dtype="float64"),
+                                _dev(stats["restart"], "stats.restart", dtype="uint8"), cap))
+    status = _lib.lalm_iterate(plan.handle, ctypes.byref(prob), ctypes.byref(st), int(n_steps),
+                               ctypes.byref(opt), sp, _stream(stream))
+    state.step, state.l, state.rho = st.step, st.l, st.rho
+    _check(status)
+    return state
+
+
+def lalm_cost_f64(plan, y, w, beta, delta, x, out, stream=None):
+    """out (float64 GPU tensor, 3 elements) = (Psi, data term, R)."""
+    prob = _problem(plan, y, w, None, beta, delta, True)
+    _check(_lib.lalm_cost_f64(plan.handle, ctypes.byref(prob), _dev(x, "x", numel=plan.image_elems),
+                              _dev(out, "out", dtype="float64", numel=3), _stream(stream)))
+
+
+def lalm_dot_f64(plan, a, b, out, stream=None):
+    n = min(a.numel(), b.numel())
+    _check(_lib.lalm_dot_f64(plan.handle, _dev(a, "a"), _dev(b, "b"), int(n),
+                             _dev(out, "out", dtype="float64", numel=1), _stream(stream)))
+
+
+def lalm_roi_rmsd_f64(plan, a, b, radius_mm, out, stream=None):
+    _check(_lib.lalm_roi_rmsd_f64(plan.handle, _dev(a, "a", numel=plan.image_elems),
+                                  _dev(b, "b", numel=plan.image_elems), float(radius_mm),
+                                  _dev(out, "out", dtype="float64", numel=1), _stream(stream)))
+
+
+def lalm_profile_begin(plan):
+    _check(_lib.lalm_profile_begin(plan.handle))
+
+
+def lalm_profile_read(plan):
+    """Per kernel class (update, project, backproject): total ms and counts."""
+    ms = np.zeros(3, dtype=np.float64)
+    n = np.zeros(3, dtype=np.int64)
+    _check(_lib.lalm_profile_read(plan.handle, ms.ctypes.data_as(ctypes.c_void_p),
+                                  n.ctypes.data_as(ctypes.c_void_p)))
+    return ms, n
+
+
+def lalm_profile_end(plan):
+    _check(_lib.lalm_profile_end(plan.handle))

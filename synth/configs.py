@@ -97,7 +97,7 @@ BETA_REL = 2.0 ** -4
 DL_MEDIAN = {
     "fan2d_128": 1.152e9,
     "fan2d_512": 1.446e9,
-    "cone_axial_512x64": None,
+    "cone_axial_512x64": 2.781e10,
     "cone_helical_512x256": None,
     "tiny2d": 1.188e6,
     "tiny3d": 4.765e5,

@@ -1,0 +1,328 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 kernels vs FP64 oracle):
+* projections and back-projections: relative L2 error <= 1e-5 per subset,
+  and max abs error <= 1e-5 x max |oracle|;
+* adjoint test on the GPU (FP32 kernels, FP64 inner products):
+  |<A x, r> - <x, A' r>| <= 1e-6 x |<A x, r>|;
+* Joseph sample counts and subset bookkeeping: exact;
+* images after a fixed number of OS-LALM iterations: ROI RMS difference
+  <= 0.5 HU (free-running), also reported with the oracle's restart sequence
+  replayed;
+* cost: relative 1e-4 (the weighted residual A x - y cancels about four
+  digits of FP32 against the data).
+"""
+import numpy as np
+import pytest
+
+from _helpers import ensure_built, rel_l2, say
+
+import oracle as ora
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    ensure_built()
+    from paper_1402_4381_amd import lalm
+    assert torch.cuda.is_available()
+    return lalm
+
+
+DEV = "cuda:0"
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV).to(dtype).contiguous()
+
+
+MED3D = dict(nx=64, ny=64, nz=16, dx=7.84, dy=7.84, dz=2.5, n_views=24, n_views_per_turn=24,
+             n_bins=111, ds=8.0, n_rows=16, dt=4.4, n_ellipses=12)
+MEDHEL = dict(nx=48, ny=48, nz=24, dx=10.0, dy=10.0, dz=5.0, n_views=72, n_views_per_turn=24,
+              n_bins=101, ds=9.0, n_rows=12, dt=8.0, pitch=1.0, n_ellipses=8)
+RAGGED2D = dict(nx=37, ny=29, dx=2.9, dy=3.3, n_views=90, n_views_per_turn=90, n_bins=101, ds=2.9)
+
+CASES = [
+    ("tiny2d", {}, 3),
+    ("tiny3d", {}, 2),
+    ("tiny_helical", {}, 4),
+    ("fan2d_128", {}, 4),
+    ("fan2d_128", RAGGED2D, 7),             # ragged tiles, ragged subsets
+    ("cone_axial_512x64", MED3D, 5),
+    ("cone_helical_512x256", MEDHEL, 6),
+]
+
+
+def _image(cfg, seed=0):
+    ph = synth.make_phantom(cfg)
+    x = synth.pixelize(cfg, ph, ss=2)
+    rng = np.random.default_rng(seed)
+    return x + rng.uniform(0.0, 0.002, x.shape)
+
+
+@pytest.mark.parametrize("name,over,M", CASES)
+def test_project_backproject_parity(L, name, over, M):
+    cfg = synth.get_config(name, **over)
+    say("case", name, over, "M", M)
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    # subset bookkeeping
+    subs = ora.subset_views(cfg["n_views"], M)
+    assert list(plan.order) == list(ora.bit_reversal_order(M))
+    x = _image(cfg)
+    xg = gpu(x)
+    rng = np.random.default_rng(1)
+    for m in range(M):
+        views = plan.subset_views(m)
+        assert list(views) == list(subs[m])
+        assert int(plan.subset_samples[m]) == ora.count_samples(cfg, views)
+        ref = ora.forward(cfg, x, views)
+        out = torch.empty(plan.subset_rays(m), device=DEV)
+        L.lalm_project_subset(plan, m, xg, out)
+        got = out.cpu().numpy().reshape(ref.shape)
+        e = rel_l2(got, ref)
+        say("  fp m=%d rel=%.2e" % (m, e))
+        assert e <= 1e-5
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+        r = rng.normal(size=ref.shape)
+        refb = ora.back(cfg, r, views)
+        xb = torch.empty(plan.image_elems, device=DEV)
+        L.lalm_backproject_subset(plan, m, gpu(r).reshape(-1), xb, scale=1.0)
+        gotb = xb.cpu().numpy().reshape(refb.shape)
+        eb = rel_l2(gotb, refb)
+        say("  bp m=%d rel=%.2e" % (m, eb))
+        assert eb <= 1e-5
+        assert np.abs(gotb - refb).max() <= 1e-5 * np.abs(refb).max()
+
+
+@pytest.mark.parametrize("name,over,M", [CASES[0], CASES[3], CASES[5], CASES[6]])
+def test_residual_mode_and_accumulate(L, name, over, M):
+    cfg = synth.get_config(name, **over)
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    x = _image(cfg)
+    rng = np.random.default_rng(2)
+    m = M - 1
+    views = plan.subset_views(m)
+    ref = ora.forward(cfg, x, views)
+    y = ref + rng.normal(0, 0.05, ref.shape)
+    w = rng.uniform(0.5, 3.0, ref.shape)
+    out = torch.empty(plan.subset_rays(m), device=DEV)
+    L.lalm_project_subset(plan, m, gpu(x), out, y=gpu(y).reshape(-1), w=gpu(w).reshape(-1))
+    got = out.cpu().numpy().reshape(ref.shape)
+    want = w * (ref - y)
+    assert np.abs(got - want).max() <= 1e-5 * np.abs(ref).max() * w.max()
+    # accumulate = 1 adds to what is there
+    r = rng.normal(size=ref.shape)
+    base = rng.normal(size=ora.image_shape(cfg))
+    xb = gpu(base).reshape(-1)
+    L.lalm_backproject_subset(plan, m, gpu(r).reshape(-1), xb, scale=2.5, accumulate=True)
+    want = base + 2.5 * ora.back(cfg, r, views)
+    assert rel_l2(xb.cpu().numpy().reshape(want.shape), want) <= 1e-5
+
+
+@pytest.mark.parametrize("name,over,M", [CASES[3], CASES[4], CASES[5], CASES[6]])
+def test_adjoint_identity_on_gpu(L, name, over, M):
+    cfg = synth.get_config(name, **over)
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    rng = np.random.default_rng(3)
+    xg = gpu(rng.uniform(0, 1, ora.image_shape(cfg))).reshape(-1)
+    for m in range(M):
+        n = plan.subset_rays(m)
+        rg = gpu(rng.normal(size=n))
+        ax = torch.empty(n, device=DEV)
+        L.lalm_project_subset(plan, m, xg, ax)
+        atr = torch.empty(plan.image_elems, device=DEV)
+        L.lalm_backproject_subset(plan, m, rg, atr)
+        d = torch.zeros(2, dtype=torch.float64, device=DEV)
+        L.lalm_dot_f64(plan, ax, rg, d[0:1])
+        L.lalm_dot_f64(plan, xg, atr, d[1:2])
+        a, b = d.cpu().numpy()
+        say("  adjoint m=%d <Ax,r>=%.9e <x,A'r>=%.9e rel=%.2e" % (m, a, b, abs(a - b) / abs(a)))
+        assert abs(a - b) <= 1e-6 * abs(a)
+
+
+def _problem(cfg, seed=None):
+    d = synth.make_problem_data(cfg, seed=seed, workers=1)
+    return d
+
+
+def _gpu_problem(L, cfg, M, data):
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    y = gpu(data["y"][plan.view_of_slot]).reshape(-1)
+    w = gpu(data["w"][plan.view_of_slot]).reshape(-1)
+    denom = torch.empty(plan.image_elems, device=DEV)
+    L.lalm_sqs_denom(plan, w, denom)
+    return plan, y, w, denom
+
+
+@pytest.mark.parametrize("name,over,M", [CASES[0], CASES[3], CASES[5]])
+def test_sqs_denominator_and_cost(L, name, over, M):
+    cfg = synth.get_config(name, **over)
+    data = _problem(cfg)
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    ref = ora.sqs_denom(cfg, data["w"])
+    got = denom.cpu().numpy().reshape(ref.shape)
+    assert rel_l2(got, ref) <= 1e-5
+    x = _image(cfg)
+    beta = 1e-3 * float(np.median(ref[ref > 0]))
+    delta = synth.configs.delta_mu(cfg)
+    out = torch.zeros(3, dtype=torch.float64, device=DEV)
+    L.lalm_cost_f64(plan, y, w, beta, delta, gpu(x).reshape(-1), out)
+    c = out.cpu().numpy()
+    # the oracle sees the same FP32-rounded image
+    xr = gpu(x).cpu().numpy().astype(np.float64)
+    cr = np.array(ora.cost(cfg, xr, data["y"], data["w"], beta, delta))
+    say("cost gpu", c, "oracle", cr)
+    assert abs(c[2] - cr[2]) <= 1e-9 * abs(cr[2])          # regularizer: FP64 from the same image
+    assert abs(c[1] - cr[1]) <= 1e-4 * abs(cr[1])
+    assert abs(c[0] - cr[0]) <= 1e-4 * abs(cr[0])
+
+
+def _run_both(L, cfg, M, n_iter, continuation=True, rho_fixed=1.0, seed=None):
+    data = _problem(cfg, seed)
+    beta = cfg["beta"]
+    delta = synth.configs.delta_mu(cfg)
+    n_steps = n_iter * M
+    ref = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=n_steps,
+                      continuation=continuation, rho_fixed=rho_fixed)
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    stats = dict(rho=torch.zeros(n_steps, dtype=torch.float64, device=DEV),
+                 xi=torch.zeros(n_steps, dtype=torch.float64, device=DEV),
+                 restart=torch.zeros(n_steps, dtype=torch.uint8, device=DEV))
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st, n_steps, continuation=continuation,
+                   rho_fixed=rho_fixed, stats=stats)
+    return data, ref, plan, (y, w, denom, beta, delta), st, stats
+
+
+def _report(cfg, ref, st, stats):
+    mask = synth.roi_mask(cfg)
+    xg = st.x.cpu().numpy().reshape(ora.image_shape(cfg))
+    d = ora.rmsd_hu(xg, ref["x"], mask, synth.HU_PER_MU)
+    rs = stats["restart"].cpu().numpy().astype(bool)
+    xi = stats["xi"].cpu().numpy()
+    mism = int(np.sum(rs != ref["restart"]))
+    return d, mism, rs, xi
+
+
+@pytest.mark.parametrize("name,M,n_iter", [("fan2d_128", 4, 20), ("tiny2d", 3, 10)])
+def test_os_lalm_parity_free_running_and_replay(L, name, M, n_iter):
+    cfg = synth.get_config(name)
+    data, ref, plan, prob, st, stats = _run_both(L, cfg, M, n_iter)
+    d, mism, rs, xi = _report(cfg, ref, st, stats)
+    say("%s free-running: RMSD %.4f HU, restart mismatches %d / %d, restarts %d"
+        % (name, d, mism, len(rs), int(rs.sum())))
+    assert d <= 0.5
+    # replay the oracle's restart sequence on the GPU
+    y, w, denom, beta, delta = prob
+    st2 = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    forced = gpu(ref["restart"].astype(np.uint8), torch.uint8)
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st2, len(ref["restart"]), forced_restart=forced)
+    d2 = ora.rmsd_hu(st2.x.cpu().numpy().reshape(ora.image_shape(cfg)), ref["x"],
+                     synth.roi_mask(cfg), synth.HU_PER_MU)
+    say("%s replay: RMSD %.4f HU" % (name, d2))
+    assert d2 <= 0.5
+    rho_g = stats["rho"].cpu().numpy()
+    if mism == 0:
+        np.testing.assert_allclose(rho_g, ref["rho"], rtol=1e-12)
+
+
+@pytest.mark.timeout(900)
+def test_os_lalm_parity_fan2d_512(L):
+    cfg = synth.get_config("fan2d_512")
+    data, ref, plan, prob, st, stats = _run_both(L, cfg, cfg["M"], cfg["n_iter"])
+    d, mism, rs, xi = _report(cfg, ref, st, stats)
+    say("fan2d_512 free-running: RMSD %.4f HU, restart mismatches %d / %d" % (d, mism, len(rs)))
+    assert d <= 0.5
+
+
+def test_fixed_rho_parity(L):
+    cfg = synth.get_config("fan2d_128")
+    data, ref, plan, prob, st, stats = _run_both(L, cfg, 4, 10, continuation=False, rho_fixed=0.1)
+    d, mism, rs, xi = _report(cfg, ref, st, stats)
+    assert d <= 0.5
+    assert np.all(stats["rho"].cpu().numpy() == 0.1)
+
+
+def test_single_subset_rho_one_cost_monotone(L):
+    cfg = synth.get_config("fan2d_128", nx=64, ny=64, dx=2.0, dy=2.0, n_views=90,
+                           n_views_per_turn=90, n_bins=128, ds=2.4, beta=None)
+    data = _problem(cfg)
+    plan, y, w, denom = _gpu_problem(L, cfg, 1, data)
+    dn = denom.cpu().numpy()
+    beta = synth.configs.BETA_REL * float(np.median(dn[synth.roi_mask(cfg).ravel()]))
+    delta = synth.configs.delta_mu(cfg)
+    st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    out = torch.zeros(3, dtype=torch.float64, device=DEV)
+    costs = []
+    for k in range(30):
+        L.lalm_iterate(plan, y, w, denom, beta, delta, st, 1, continuation=False, rho_fixed=1.0)
+        L.lalm_cost_f64(plan, y, w, beta, delta, st.x, out)
+        costs.append(float(out[0].item()))
+    c = np.array(costs)
+    assert np.all(np.diff(c) <= 1e-6 * abs(c[0]))
+    assert c[-1] < c[0]
+
+
+def test_determinism_and_checkpoint_resume(L):
+    cfg = synth.get_config("fan2d_128")
+    data = _problem(cfg)
+    plan, y, w, denom = _gpu_problem(L, cfg, 4, data)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    z = torch.zeros(plan.image_elems, device=DEV)
+    a = L.LalmState.zeros_like(z.clone())
+    L.lalm_iterate(plan, y, w, denom, beta, delta, a, 40)
+    b = L.LalmState.zeros_like(z.clone())
+    L.lalm_iterate(plan, y, w, denom, beta, delta, b, 40)
+    assert torch.equal(a.x, b.x) and torch.equal(a.g, b.g) and a.rho == b.rho and a.l == b.l
+    c = L.LalmState.zeros_like(z.clone())
+    L.lalm_iterate(plan, y, w, denom, beta, delta, c, 17)
+    saved = c.clone()
+    del c
+    plan2 = L.lalm_plan_geometry(synth.geometry_of(cfg), 4)    # resume on a fresh plan
+    L.lalm_iterate(plan2, y, w, denom, beta, delta, saved, 23)
+    assert saved.step == 40
+    assert torch.equal(a.x, saved.x) and torch.equal(a.g, saved.g) and torch.equal(a.grad, saved.grad)
+    assert a.rho == saved.rho and a.l == saved.l
+
+
+def test_nonfinite_data_is_reported_and_image_stays_finite(L):
+    cfg = synth.get_config("fan2d_128")
+    data = _problem(cfg)
+    plan, y, w, denom = _gpu_problem(L, cfg, 4, data)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st, 6)
+    good = st.x.clone()
+    ybad = y.clone()
+    s = plan.subset_slice(int(plan.order[(st.step + 1) % 4]))
+    ybad[s.start + 100] = float("nan")
+    with pytest.raises(L.LalmError) as ei:
+        L.lalm_iterate(plan, ybad, w, denom, beta, delta, st, 5)
+    assert ei.value.status == L.LALM_E_NONFINITE
+    assert torch.isfinite(st.x).all()
+    assert st.step == 7
+    # the failing step's image update used finite gradients
+    assert not torch.equal(st.x, good)
+
+
+def test_edge_cases(L):
+    # every subset a single view; one subset; zero steps
+    cfg = synth.get_config("tiny2d")
+    data = _problem(cfg)
+    for M in (1, cfg["n_views"]):
+        plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+        st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+        L.lalm_iterate(plan, y, w, denom, 1e-3, 2e-4, st, 0)
+        assert st.step == 0 and torch.count_nonzero(st.x) == 0
+        assert torch.count_nonzero(st.grad) > 0
+        L.lalm_iterate(plan, y, w, denom, 1e-3, 2e-4, st, 2 * M)
+        assert st.step == 2 * M and torch.isfinite(st.x).all()
+    with pytest.raises(L.LalmError):
+        L.lalm_iterate(plan, y, w, denom, 1e-3, 2e-4, st, 1, n_inner=2)
+    with pytest.raises(L.LalmError):
+        L.lalm_project_subset(plan, M, torch.zeros(plan.image_elems, device=DEV),
+                              torch.zeros(16, device=DEV))

@@ -1,0 +1,82 @@
+"""CPU checks of the C ABI: the header compiles as C, the built library
+exports every declared call, the binding exposes the same names, and
+argument validation fails cleanly before any GPU work is queued."""
+import ctypes
+import subprocess
+
+import pytest
+
+from _helpers import HEADER, LIB, ensure_built, header_functions
+
+import synth
+
+
+@pytest.fixture(scope="module")
+def lib():
+    ensure_built()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_is_plain_c():
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER])
+
+
+def test_every_declared_call_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], stdout=subprocess.PIPE, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for n in names:
+        assert n in exported, n
+        getattr(lib, n)
+    # internal launchers stay hidden
+    assert not any("launch_fp" in e for e in exported)
+
+
+def test_binding_names_match_header(lib):
+    from paper_1402_4381_amd import lalm
+    for n in header_functions():
+        assert hasattr(lalm, n), n
+    assert set(lalm.EXPORTS) == set(header_functions())
+
+
+def _geom(**kw):
+    from paper_1402_4381_amd import lalm
+    g = synth.geometry_of(synth.get_config("fan2d_128"))
+    g.update(kw)
+    return lalm._geometry(g)
+
+
+@pytest.mark.parametrize("kw,M", [
+    (dict(nx=0), 4),
+    (dict(dsd=500.0), 4),            # dsd <= dso
+    (dict(dso=60.0, dsd=120.0), 4),  # source inside the image's circumscribed circle
+    (dict(detector=1), 4),
+    (dict(nz=2), 4),                 # 2D needs nz = 1
+    (dict(n_rows=3), 4),
+    ({}, 0),
+    ({}, 181),                       # more subsets than views
+    (dict(dx=-1.0), 4),
+    (dict(kind=7), 4),
+])
+def test_invalid_geometry_rejected_before_gpu_work(lib, kw, M):
+    from paper_1402_4381_amd import lalm
+    h = ctypes.c_void_p()
+    st = lalm._lib.lalm_plan_geometry(ctypes.byref(_geom(**kw)), M, ctypes.byref(h))
+    assert st == lalm.LALM_E_INVALID
+    assert h.value is None
+    assert len(lalm.lalm_last_error()) > 0
+
+
+def test_null_arguments_rejected(lib):
+    from paper_1402_4381_amd import lalm
+    L = lalm._lib
+    assert L.lalm_plan_geometry(None, 4, None) == lalm.LALM_E_INVALID
+    assert L.lalm_plan_info(None, None, None, None, None, None, None) == lalm.LALM_E_INVALID
+    assert L.lalm_project_subset(None, 0, None, None, None, None, None) == lalm.LALM_E_INVALID
+    assert L.lalm_backproject_subset(None, 0, None, None, 1.0, 0, None) == lalm.LALM_E_INVALID
+    assert L.lalm_sqs_denom(None, None, None, None) == lalm.LALM_E_INVALID
+    assert L.lalm_iterate(None, None, None, 1, None, None, None) == lalm.LALM_E_INVALID
+    assert L.lalm_dot_f64(None, None, None, 0, None, None) == lalm.LALM_E_INVALID
+    assert L.lalm_plan_destroy(None) == lalm.LALM_E_INVALID
+    assert lalm.lalm_version().startswith("lalm")
