@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--workload", default="fan2d_512")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the multi-GPU path is not built (see DESIGN.md).",
@@ -91,6 +93,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = "cuda:0"
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, device=dev)     # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": src.numel() * 4}))
+        return
     cfg = synth.get_config(args.workload)
     M = cfg["M"]
     log("bench: generating %s inputs" % args.workload)

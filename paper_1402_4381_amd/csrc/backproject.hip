@@ -15,8 +15,10 @@
 //   BP_INIT   G = g = M A_m' r, grad R(x); FP64 sum of G^2 (finite check)
 //   BP_STEP   G+ = M A_m' r;  xi partial (g - G+)(G+ - G) in FP64;
 //             g <- (rho G+ + g) / (rho + 1);  G <- G+;  grad R(x)
-// The last block to finish (device-wide counter) reduces the FP64 partials in
-// a fixed order and performs the continuation update of Sec. III-B.
+// Every block writes its FP64 partial sum; a one-block finalize kernel then
+// reduces the partials in a fixed order and performs the continuation update
+// of Sec. III-B (the kernel boundary orders the partial stores before the
+// reduction without a device-scope fence per block).
 #include "lalm_internal.h"
 
 namespace lalm {
@@ -34,9 +36,11 @@ struct BPArgs {
     const float *r;
     BpEpi e;
     double *partials;
-    unsigned int *counter;
     DevScalars *sc;
     int nblocks;
+    float *part;       // 2D: back-projection of the x-dominant rays
+    float *part2;      // 2D: back-projection of the y-dominant rays
+    int check_status;  // 2D line kernel: skip when a non-finite indicator was met
 };
 
 // d psi / dt for the hyperbola potential: t / sqrt(1 + (t/delta)^2)
@@ -86,6 +90,46 @@ __device__ inline double block_sum_256(double v, double *lds)
     return t;   // valid in thread 0
 }
 
+// Last block of a back-projection: continuation update of Sec. III-B from
+// the FP64 total of the restart indicator (STEP) or the finite check (INIT).
+template <int MODE>
+__device__ void finalize_continuation(const BPArgs &A, double total)
+{
+    DevScalars *sc = A.sc;
+    const ContArgs &C = A.e.cont;
+    if (MODE == BP_INIT) {
+        if (!isfinite(total)) sc->status = 1;
+    } else {
+        const long long jstep = sc->step;
+        const double rho_used = sc->rho;
+        bool restart = false;
+        if (!isfinite(total)) {
+            sc->status = 1;
+        } else if (C.continuation) {
+            restart = total > 0.0;
+            if (C.forced && jstep < C.forced_len) restart = C.forced[jstep] != 0;
+            const long long l = restart ? 0 : sc->l + 1;
+            sc->l = l;
+            double nr;
+            if (l == 0) {
+                nr = 1.0;
+            } else {
+                const double pi = 3.14159265358979323846;
+                const double a = pi / (2.0 * (double)(l + 1));
+                nr = fmax(pi / (double)(l + 1) * sqrt(1.0 - a * a), C.rho_min);
+            }
+            sc->rho = nr;
+        }
+        sc->xi = total;
+        if (jstep < C.st_cap) {
+            if (C.st_rho) C.st_rho[jstep] = rho_used;
+            if (C.st_xi) C.st_xi[jstep] = total;
+            if (C.st_restart) C.st_restart[jstep] = restart ? 1 : 0;
+        }
+        sc->step = jstep + 1;
+    }
+}
+
 template <bool IS3D, int MODE>
 __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 {
@@ -100,8 +144,6 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 
     __shared__ float s_rowv[256], s_rowf[256];
     __shared__ double s_red[4];
-    __shared__ double s_tree[256];
-    __shared__ int s_last;
     if (IS3D) {
         for (int t = tid; t < K.nr; t += 256) { s_rowv[t] = A.rowv[t]; s_rowf[t] = A.rowf[t]; }
         __syncthreads();
@@ -198,70 +240,262 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 
     const double bsum = block_sum_256(part, s_red);
     const int blin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    if (tid == 0) {
-        __hip_atomic_store(&A.partials[blin], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned prev = atomicAdd(A.counter, 1u);
-        s_last = (prev == (unsigned)A.nblocks - 1u);
+    if (tid == 0) A.partials[blin] = bsum;
+}
+
+// ------------------------------------------------------------------------
+// 2D back-projection by line owners.
+//
+// The x-dominant rays of a view sample every image column i at
+// eta = a_b + i c_b and put their two taps on rows floor(eta), floor(eta)+1 of
+// that column; the y-dominant rays do the same along rows.  One launch covers
+// both classes: blocks [0, nxt) own tiles of 64 columns x TR rows (a lane owns
+// a column and takes the x-dominant rays), the remaining blocks own tiles of
+// TR columns x 64 rows (a lane owns a row and takes the y-dominant rays).  The
+// waves of a block take interleaved views.  For a view, each lane finds the
+// channels whose rays cross its line inside the tile's band (channel
+// coordinates of the band's two end points seen from the source); the wave
+// stages the union of those rays (a, c, sc * r) in its own LDS buffer with
+// coalesced loads, then every lane walks its rays in channel order and
+// accumulates into its own LDS column.  No two lanes write one accumulator:
+// no atomics, fixed summation order.  Waves are summed in wave order and the
+// tile is written to the partial image of its class; a pointwise epilogue
+// kernel adds the two partial images and applies the OS-LALM update.
+constexpr int BP2_VG = 8;      // waves (view groups) per block
+constexpr int BP2_TR = 16;     // band width of a tile
+constexpr int BP2_LD = 66;     // LDS stride between accumulator rows (bank spread)
+constexpr int BP2_ROWS = BP2_TR + 4;   // two padding rows on each side of the band
+constexpr int BP2_WMAX = 256;  // staged rays per wave and view
+
+// atan(t) = t P(t^2) on [0, 1] with a degree-5 polynomial P fitted by
+// reweighted least squares on Chebyshev nodes (max error 1.7e-6 rad), and
+// atan(t) = pi/2 - atan(1/t) above 1.  Used only to bound channel windows;
+// the window margin covers its error.
+__device__ inline float atan_window(float t)
+{
+    const float at = fabsf(t);
+    const bool big = at > 1.0f;
+    const float z = big ? __frcp_rn(at) : at;
+    const float z2 = z * z;
+    float p = fmaf(z2, -0.011719409376382828f, 0.05264794081449509f);
+    p = fmaf(z2, p, -0.11642685532569885f);
+    p = fmaf(z2, p, 0.19354040920734406f);
+    p = fmaf(z2, p, -0.33262279629707336f);
+    p = fmaf(z2, p, 0.9999772310256958f);
+    float r = z * p;
+    r = big ? 1.5707963267948966f - r : r;
+    return copysignf(r, t);
+}
+
+// Continuous channel coordinate of the ray from the view's source through
+// the point (px, py).  The point lies in front of the source (dc > 0).
+__device__ inline float bin_coord(const GeoK &K, const ViewRec &V, float px, float py)
+{
+    const float ddx = px - V.sx, ddy = py - V.sy;
+    const float dc = -(ddx * V.cb + ddy * V.sb);
+    const float dp = ddx * V.sb - ddy * V.cb;
+    return fmaf(atan_window(__fdividef(dp, dc)), K.dsd_over_ds, K.bin_center);
+}
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Two taps of one sample into the lane's accumulator column.  jj is the lower
+// tap's row relative to the band; rows outside the band land in the padding.
+// Accumulator slot of (row, lane) in a wave's slab.
+__device__ inline int acc_slot(int row, int lane) { return row * BP2_LD + lane; }
+
+__device__ inline void splat2(float *slab, int lane, int jj, float f, float val)
+{
+    jj = min(max(jj, -2), BP2_TR);
+    slab[acc_slot(jj + 2, lane)] += (1.0f - f) * val;
+    slab[acc_slot(jj + 3, lane)] += f * val;
+}
+__global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int nxt)
+{
+    const GeoK &K = A.k;
+    if (A.check_status && A.sc->status) return;
+    __shared__ float acc[BP2_VG][BP2_ROWS][BP2_LD];
+    __shared__ float4 stage[BP2_VG][BP2_WMAX];
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int tid = lane + 64 * wv;
+    for (int t = tid; t < BP2_VG * BP2_ROWS * BP2_LD; t += 64 * BP2_VG) (&acc[0][0][0])[t] = 0.0f;
+    __syncthreads();
+
+    const bool ypass = (int)blockIdx.x >= nxt;
+    const int tb = ypass ? (int)blockIdx.x - nxt : (int)blockIdx.x;
+    // X pass: own = column, band = rows.  Y pass: own = row, band = columns.
+    const int ntx = ypass ? (K.nx + BP2_TR - 1) / BP2_TR : (K.nx + 63) / 64;
+    const int own_base = (ypass ? tb / ntx : tb % ntx) * 64;
+    const int band_base = (ypass ? tb % ntx : tb / ntx) * BP2_TR;
+    const int n_own = ypass ? K.ny : K.nx;
+    const int own = own_base + lane;
+    const bool active = own < n_own;
+    float *slab = &acc[wv][0][0];
+    float4 *st = stage[wv];
+    const float own_c = ypass ? fmaf((float)own, K.dy, K.y0) : fmaf((float)own, K.dx, K.x0);
+    const float e1 = ypass ? fmaf((float)(band_base - 1), K.dx, K.x0) : fmaf((float)(band_base - 1), K.dy, K.y0);
+    const float e2 = ypass ? fmaf((float)(band_base + BP2_TR), K.dx, K.x0)
+                           : fmaf((float)(band_base + BP2_TR), K.dy, K.y0);
+    const float sf = (float)own;
+    const int last = min(63, n_own - 1 - own_base);   // last active lane
+
+    for (int kv = wv; kv < A.nview; kv += BP2_VG) {
+        const ViewRec V = A.views[kv];
+        const int blo = ypass ? V.by0 : V.bx0, bhi = ypass ? V.by1 : V.bx1;
+        if (blo >= bhi) continue;                      // uniform across the wave
+        int b0 = bhi, b1 = blo - 1;
+        float u1 = 0.0f, u2 = 0.0f;
+        if (active) {
+            u1 = ypass ? bin_coord(K, V, e1, own_c) : bin_coord(K, V, own_c, e1);
+            u2 = ypass ? bin_coord(K, V, e2, own_c) : bin_coord(K, V, own_c, e2);
+            b0 = max(blo, (int)ceilf(fminf(u1, u2) - K.bin_margin));
+            b1 = min(bhi - 1, (int)floorf(fmaxf(u1, u2) + K.bin_margin));
+        }
+        // union window of the wave: the channel coordinate over the tile's
+        // band rectangle is extremal at its corners, held by the first and
+        // the last active lane
+        const float c1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u1), 0));
+        const float c2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u2), 0));
+        const float c3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u1), last));
+        const float c4 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u2), last));
+        const float umin = fminf(fminf(c1, c2), fminf(c3, c4)), umax = fmaxf(fmaxf(c1, c2), fmaxf(c3, c4));
+        const int wlo = max(blo, (int)ceilf(umin - K.bin_margin - 0.01f));
+        const int whi = min(bhi - 1, (int)floorf(umax + K.bin_margin + 0.01f));
+        if (whi < wlo) continue;
+        b0 = max(b0, wlo);                             // keep every lane inside the union
+        b1 = min(b1, whi);
+        const RayRec *R = A.rays + (long long)kv * K.nb;
+        const float *rv = A.r + (long long)kv * K.nb;
+        if (whi - wlo + 1 <= BP2_WMAX) {
+            wave_lds_sync();                           // previous view's readers are done
+            for (int t = lane; t <= whi - wlo; t += 64) {
+                const RayRec q = R[wlo + t];
+                st[t] = make_float4(q.a, q.c, q.sc * rv[wlo + t], 0.0f);
+            }
+            wave_lds_sync();
+            // lanes whose window lies outside the union never happen (the
+            // union covers every lane), so st[b - wlo] stays in range
+            int b = b0;
+            for (; b + 3 <= b1; b += 4) {
+                float4 q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[u] = st[b + u - wlo];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float eta = fmaf(sf, q[u].y, q[u].x);
+                    const float fl = floorf(eta);
+                    splat2(slab, lane, (int)fl - band_base, eta - fl, q[u].z);
+                }
+            }
+            for (; b <= b1; ++b) {
+                const float4 q0 = st[b - wlo];
+                const float eta0 = fmaf(sf, q0.y, q0.x);
+                const float fl0 = floorf(eta0);
+                splat2(slab, lane, (int)fl0 - band_base, eta0 - fl0, q0.z);
+            }
+        } else {
+            for (int b = b0; b <= b1; ++b) {           // wide window: read rays directly
+                const RayRec q = R[b];
+                const float eta = fmaf(sf, q.c, q.a);
+                const float fl = floorf(eta);
+                splat2(slab, lane, (int)fl - band_base, eta - fl, q.sc * rv[b]);
+            }
+        }
     }
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // fixed-order reduction of the block partials
+
+    // sum the waves in order and write the tile to its class's partial image
+    float *outp = ypass ? A.part2 : A.part;
+    for (int t = tid; t < BP2_TR * 64; t += 64 * BP2_VG) {
+        const int bnd = ypass ? (t % BP2_TR) : (t / 64);   // consecutive threads walk along x
+        const int ow = ypass ? (t / BP2_TR) : (t % 64);
+        const int i = ypass ? band_base + bnd : own_base + ow;
+        const int j = ypass ? own_base + ow : band_base + bnd;
+        if (i >= K.nx || j >= K.ny) continue;
+        const int slot = acc_slot(bnd + 2, ow);
+        float sacc = (&acc[0][0][0])[slot];
+#pragma unroll
+        for (int w2 = 1; w2 < BP2_VG; ++w2) sacc += (&acc[w2][0][0])[slot];
+        outp[(long long)j * K.nx + i] = sacc;
+    }
+}
+
+// Pointwise epilogue of the 2D back-projection: total = part_x + part_y, then
+// PLAIN (out = scale * total, or +=), INIT or STEP as in the 3D kernel.
+template <int MODE>
+__global__ void __launch_bounds__(256) bp2d_epilogue_kernel(BPArgs A)
+{
+    const GeoK &K = A.k;
+    if (MODE != BP_PLAIN && A.sc->status) return;
+    __shared__ double s_red[4];
+    const int tid = threadIdx.x + 32 * threadIdx.y;
+    const int i = blockIdx.x * 32 + threadIdx.x, j = blockIdx.y * 8 + threadIdx.y;
+    double part = 0.0;
+    if (i < K.nx && j < K.ny) {
+        const long long idx = (long long)j * K.nx + i;
+        const float total = A.part[idx] + A.part2[idx];
+        if (MODE == BP_PLAIN) {
+            const float vv = A.e.scale * total;
+            A.e.out[idx] = A.e.accumulate ? A.e.out[idx] + vv : vv;
+        } else if (MODE == BP_INIT) {
+            const float Gv = A.e.scale * total;
+            A.e.G[idx] = Gv;
+            A.e.g[idx] = Gv;
+            A.e.out[idx] = reg_grad_at<false>(K, A.e.x, i, j, 0, A.e.beta, A.e.inv_delta2);
+            part = (double)Gv * (double)Gv;
+        } else {
+            const float rho = (float)A.sc->rho;
+            const float Gn = A.e.scale * total;
+            const float Go = A.e.G[idx], gv = A.e.g[idx];
+            part = ((double)gv - (double)Gn) * ((double)Gn - (double)Go);
+            A.e.g[idx] = fmaf(rho, Gn, gv) / (rho + 1.0f);
+            A.e.G[idx] = Gn;
+            A.e.out[idx] = reg_grad_at<false>(K, A.e.x, i, j, 0, A.e.beta, A.e.inv_delta2);
+        }
+    }
+    if (MODE == BP_PLAIN) return;
+    const double bsum = block_sum_256(part, s_red);
+    const int blin = blockIdx.x + gridDim.x * blockIdx.y;
+    if (threadIdx.x + 32 * threadIdx.y == 0) A.partials[blin] = bsum;
+}
+
+// One block: fixed-order FP64 sum of the back-projection's block partials,
+// then the continuation update (STEP) or the finite check (INIT).
+template <int MODE>
+__global__ void __launch_bounds__(256) finalize_kernel(BPArgs A)
+{
+    if (A.sc->status) return;
+    __shared__ double s_tree[256];
+    const int tid = threadIdx.x;
     double v = 0.0;
-    for (int t = tid; t < A.nblocks; t += 256)
-        v += __hip_atomic_load(&A.partials[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int t = tid; t < A.nblocks; t += 256) v += A.partials[t];
     s_tree[tid] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (tid < w) s_tree[tid] += s_tree[tid + w];
         __syncthreads();
     }
-    if (tid != 0) return;
-    const double total = s_tree[0];
-    DevScalars *sc = A.sc;
-    const ContArgs &C = A.e.cont;
-    if (MODE == BP_INIT) {
-        if (!isfinite(total)) sc->status = 1;
-    } else {
-        const long long jstep = sc->step;
-        const double rho_used = sc->rho;
-        bool restart = false;
-        if (!isfinite(total)) {
-            sc->status = 1;
-        } else if (C.continuation) {
-            restart = total > 0.0;
-            if (C.forced && jstep < C.forced_len) restart = C.forced[jstep] != 0;
-            const long long l = restart ? 0 : sc->l + 1;
-            sc->l = l;
-            double nr;
-            if (l == 0) {
-                nr = 1.0;
-            } else {
-                const double pi = 3.14159265358979323846;
-                const double a = pi / (2.0 * (double)(l + 1));
-                nr = fmax(pi / (double)(l + 1) * sqrt(1.0 - a * a), C.rho_min);
-            }
-            sc->rho = nr;
-        }
-        sc->xi = total;
-        if (jstep < C.st_cap) {
-            if (C.st_rho) C.st_rho[jstep] = rho_used;
-            if (C.st_xi) C.st_xi[jstep] = total;
-            if (C.st_restart) C.st_restart[jstep] = restart ? 1 : 0;
-        }
-        sc->step = jstep + 1;
-    }
-    *A.counter = 0u;
+    if (tid == 0) finalize_continuation<MODE>(A, s_tree[0]);
 }
 
 template <bool IS3D>
 hipError_t bp_dispatch(const BPArgs &a, int mode, dim3 grd, hipStream_t st)
 {
     dim3 blk(32, 8);
-    if (mode == BP_PLAIN) hipLaunchKernelGGL((bp_kernel<IS3D, BP_PLAIN>), grd, blk, 0, st, a);
-    else if (mode == BP_INIT) hipLaunchKernelGGL((bp_kernel<IS3D, BP_INIT>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((bp_kernel<IS3D, BP_STEP>), grd, blk, 0, st, a);
+    if (mode == BP_PLAIN) {
+        hipLaunchKernelGGL((bp_kernel<IS3D, BP_PLAIN>), grd, blk, 0, st, a);
+    } else if (mode == BP_INIT) {
+        hipLaunchKernelGGL((bp_kernel<IS3D, BP_INIT>), grd, blk, 0, st, a);
+        hipLaunchKernelGGL((finalize_kernel<BP_INIT>), dim3(1), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((bp_kernel<IS3D, BP_STEP>), grd, blk, 0, st, a);
+        hipLaunchKernelGGL((finalize_kernel<BP_STEP>), dim3(1), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -291,12 +525,31 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.e = e;
     if (mode != BP_PLAIN) a.e.out = p->d_gradR;
     a.partials = p->d_partials;
-    a.counter = p->d_counter;
     a.sc = p->d_sc;
-    const int kz = p->is3d ? KZ3 : 1;
+    a.part = p->d_part;
+    a.part2 = p->d_part2;
+    a.check_status = mode != BP_PLAIN;
+    if (!p->is3d) {
+        const int nxt = ((p->nx + 63) / 64) * ((p->ny + BP2_TR - 1) / BP2_TR);
+        const int nyt = ((p->nx + BP2_TR - 1) / BP2_TR) * ((p->ny + 63) / 64);
+        hipLaunchKernelGGL(bp2d_lines_kernel, dim3(nxt + nyt), dim3(64, BP2_VG), 0, st, a, nxt);
+        dim3 ge((p->nx + 31) / 32, (p->ny + 7) / 8);
+        a.nblocks = (int)(ge.x * ge.y);
+        if (mode == BP_PLAIN) {
+            hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_PLAIN>), ge, dim3(32, 8), 0, st, a);
+        } else if (mode == BP_INIT) {
+            hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_INIT>), ge, dim3(32, 8), 0, st, a);
+            hipLaunchKernelGGL((finalize_kernel<BP_INIT>), dim3(1), dim3(256), 0, st, a);
+        } else {
+            hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_STEP>), ge, dim3(32, 8), 0, st, a);
+            hipLaunchKernelGGL((finalize_kernel<BP_STEP>), dim3(1), dim3(256), 0, st, a);
+        }
+        return hipGetLastError();
+    }
+    const int kz = KZ3;
     dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + kz - 1) / kz);
     a.nblocks = (int)(grd.x * grd.y * grd.z);
-    return p->is3d ? bp_dispatch<true>(a, mode, grd, st) : bp_dispatch<false>(a, mode, grd, st);
+    return bp_dispatch<true>(a, mode, grd, st);
 }
 
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,

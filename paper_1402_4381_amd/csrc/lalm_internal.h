@@ -29,10 +29,14 @@ struct RayRecZ {
     float m, k;
 };
 // Per slot: source position (mm, relative to the isocentre), cos/sin of the
-// view angle, and z0 = (S_z - Z_0) / dz.
+// view angle, z0 = (S_z - Z_0) / dz, and the channel ranges [bx0, bx1) and
+// [by0, by1) of the view's x-dominant and y-dominant rays (each class is one
+// contiguous range because the fan is narrower than 90 degrees).
 struct ViewRec {
     float sx, sy, cb, sb;
-    float z0, pad0, pad1, pad2;
+    float z0, pad0;
+    int bx0, bx1, by0, by1;
+    int pad1, pad2;
 };
 
 constexpr uint32_t kYDom = 0x80000000u;
@@ -61,6 +65,7 @@ struct GeoK {
     float dmax;               // max(dx, dy)
     float inv_dt;             // 1 / dt
     float row_center;         // (nr-1)/2
+    float bin_margin;         // channel-window margin (bins) for rounding and the window atan
     // padded image copies
     int ldT, ldN;             // padded length of the fastest axis: ny+4, nx+4
     long long slabT, slabN;   // elements per slice of the dominant axis
@@ -102,9 +107,10 @@ struct lalm_plan {
     float *d_xn = nullptr;              // padded copy for y-dominant rays
     float *d_gradR = nullptr;           // regularizer gradient image
     float *d_r = nullptr;               // subset residual
+    float *d_part = nullptr;            // 2D: back-projection of the x-dominant rays
+    float *d_part2 = nullptr;           // 2D: back-projection of the y-dominant rays
     double *d_partials = nullptr;       // reduction partials
     int64_t n_partials = 0;
-    unsigned int *d_counter = nullptr;  // last-block counter
     lalm::DevScalars *d_sc = nullptr;
     lalm::DevScalars *h_sc = nullptr;   // pinned host mirror
     double *d_tmp = nullptr;            // small FP64 scratch (monitors)

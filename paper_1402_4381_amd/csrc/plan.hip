@@ -87,8 +87,9 @@ static void free_plan(lalm_plan *p)
     (void)hipFree(p->d_xn);
     (void)hipFree(p->d_gradR);
     (void)hipFree(p->d_r);
+    (void)hipFree(p->d_part);
+    (void)hipFree(p->d_part2);
     (void)hipFree(p->d_partials);
-    (void)hipFree(p->d_counter);
     (void)hipFree(p->d_sc);
     (void)hipFree(p->d_tmp);
     if (p->h_sc) (void)hipHostFree(p->h_sc);
@@ -113,13 +114,14 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
         return invalid("geometry: view, bin and row counts must be positive");
     if (!(g.dso > 0 && g.dsd > g.dso)) return invalid("geometry: need 0 < dso < dsd");
     double half_diag = 0.5 * std::sqrt((double)g.nx * g.dx * g.nx * g.dx + (double)g.ny * g.dy * g.ny * g.dy);
-    if (!(g.dso > half_diag)) return invalid("geometry: source inside the image's circumscribed cylinder");
+    if (!(g.dso > half_diag + 2.0 * std::max(g.dx, g.dy)))
+        return invalid("geometry: source inside (or within two pixels of) the image's circumscribed cylinder");
     if (g.detector != 0) return invalid("geometry: only the arc detector (0) is implemented");
     if (g.kind == LALM_CONE_HELICAL && !(g.pitch >= 0)) return invalid("geometry: negative pitch");
     if (n_subsets < 1 || n_subsets > g.n_views) return invalid("n_subsets must lie in [1, n_views]");
     if (g.n_rows > 256) return invalid("geometry: at most 256 detector rows");
     double half_fan = 0.5 * g.n_bins * g.ds / g.dsd;
-    if (!(half_fan < 1.2)) return invalid("geometry: fan angle too wide");
+    if (!(half_fan < 0.75)) return invalid("geometry: fan angle too wide (half fan must stay below 0.75 rad)");
 
     lalm_plan *p = new lalm_plan();
     p->g = g;
@@ -160,6 +162,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     std::vector<lalm::RayRecZ> raysz(is3d ? (size_t)nv * nb : 0);
     std::vector<lalm::ViewRec> views(nv);
     std::vector<long long> slot_samples(nv, 0);
+    std::vector<char> slot_split(nv, 0);   // dominance classes not contiguous
 
     auto work = [&](int slot_lo, int slot_hi) {
         for (int slot = slot_lo; slot < slot_hi; ++slot) {
@@ -172,8 +175,10 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
             vw.sx = (float)Sx; vw.sy = (float)Sy;
             vw.cb = (float)std::cos(beta); vw.sb = (float)std::sin(beta);
             vw.z0 = (float)z0;
-            views[slot] = vw;
+            vw.bx0 = vw.by0 = nb;
+            vw.bx1 = vw.by1 = 0;
             long long nsamp = 0;
+            int nxdom = 0;
             for (int b = 0; b < nb; ++b) {
                 double gam = (b - (nb - 1) / 2.0 - g.channel_offset) * g.ds / g.dsd;
                 double th = beta + PI + gam;
@@ -205,6 +210,8 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
                 rr.a = (float)a; rr.c = (float)c; rr.sc = (float)sc;
                 rr.meta = (uint32_t)(k0 & 0xFFFF) | ((uint32_t)(k1 & 0x7FFF) << 16) | (xdom ? 0u : lalm::kYDom);
                 rays[(size_t)slot * nb + b] = rr;
+                if (xdom) { vw.bx0 = std::min(vw.bx0, b); vw.bx1 = std::max(vw.bx1, b + 1); ++nxdom; }
+                else { vw.by0 = std::min(vw.by0, b); vw.by1 = std::max(vw.by1, b + 1); }
                 if (is3d) {
                     raysz[(size_t)slot * nb + b] = lalm::RayRecZ{(float)m, (float)k};
                     for (int r = 0; r < nr; ++r) {
@@ -219,6 +226,11 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
                     nsamp += s1 - s0 + 1;
                 }
             }
+            if (vw.bx0 > vw.bx1) { vw.bx0 = 0; vw.bx1 = 0; }
+            if (vw.bx1 - vw.bx0 != nxdom || (nxdom > 0 && nxdom < nb && vw.bx0 != 0 && vw.bx1 != nb))
+                slot_split[slot] = 1;
+            if (vw.by0 > vw.by1) { vw.by0 = 0; vw.by1 = 0; }
+            views[slot] = vw;
             slot_samples[slot] = nsamp;
         }
     };
@@ -229,6 +241,11 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
         pool.emplace_back(work, (int)((long long)nv * t / nthr), (int)((long long)nv * (t + 1) / nthr));
     for (auto &th : pool) th.join();
 
+    for (int slot = 0; slot < nv; ++slot)
+        if (slot_split[slot]) {
+            free_plan(p);
+            return invalid("geometry: a view's rays switch dominant axis more than once");
+        }
     p->subset_samples.assign(M, 0);
     for (int m = 0; m < M; ++m)
         for (int64_t s = p->slot_offset[m]; s < p->slot_offset[m + 1]; ++s) p->subset_samples[m] += slot_samples[s];
@@ -242,6 +259,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     K.dmax = (float)std::max(g.dx, g.dy);
     K.inv_dt = (float)(1.0 / g.dt);
     K.row_center = (float)((nr - 1) / 2.0);
+    K.bin_margin = (float)(0.05 + (g.dsd / g.ds) * 4e-6);
     K.ldT = g.ny + 4;
     K.ldN = g.nx + 4;
     K.slabT = is3d ? (long long)(g.nz + 4) * K.ldT : K.ldT;
@@ -254,7 +272,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     while (p->fp_nseg < 8 && waves * p->fp_nseg < 8192) p->fp_nseg *= 2;
 
     const size_t nvox = (size_t)g.nx * g.ny * g.nz;
-    const int64_t bp_blocks = (int64_t)((g.nx + 31) / 32) * ((g.ny + 7) / 8) * (is3d ? (g.nz + 7) / 8 : 1);
+    const int64_t bp_blocks = (int64_t)((g.nx + 31) / 32) * ((g.ny + 7) / 8) * ((g.nz + 7) / 8);
     p->n_partials = std::max<int64_t>({65536, bp_blocks + 16, (p->max_subset_rays + 63) / 64 + 16,
                                        (int64_t)M + 16});
     hipError_t e = hipSuccess;
@@ -268,8 +286,9 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(dev_alloc(&p->d_xn, (size_t)g.ny * K.slabN));
     chk(dev_alloc(&p->d_gradR, nvox));
     chk(dev_alloc(&p->d_r, (size_t)p->max_subset_rays));
+    chk(dev_alloc(&p->d_part, nvox));
+    chk(dev_alloc(&p->d_part2, nvox));
     chk(dev_alloc(&p->d_partials, (size_t)p->n_partials));
-    chk(dev_alloc(&p->d_counter, 1));
     chk(dev_alloc(&p->d_sc, 1));
     chk(dev_alloc(&p->d_tmp, (size_t)(64 + M)));
     if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_sc, sizeof(lalm::DevScalars), hipHostMallocDefault);
@@ -286,7 +305,6 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(hipMemset(p->d_xt, 0, (size_t)g.nx * K.slabT * sizeof(float)));
     chk(hipMemset(p->d_xn, 0, (size_t)g.ny * K.slabN * sizeof(float)));
     chk(hipMemset(p->d_gradR, 0, nvox * sizeof(float)));
-    chk(hipMemset(p->d_counter, 0, sizeof(unsigned int)));
     chk(hipMemset(p->d_sc, 0, sizeof(lalm::DevScalars)));
     chk(hipDeviceSynchronize());
     if (e != hipSuccess) {

@@ -57,7 +57,24 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
         if (!IS3D) {
             const int ld = ydom ? K.ldN : K.ldT;
             const float *base = img + 2;
-            for (int s = s0; s <= s1; ++s) {
+            int s = s0;
+            // eight samples per round: their tap loads are independent
+            for (; s + 7 <= s1; s += 8) {
+                float v0[8], v1[8], f[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float eta = fmaf((float)(s + u), rr.c, rr.a);
+                    const float fl = floorf(eta);
+                    f[u] = eta - fl;
+                    const int j0 = min(max((int)fl, -2), lim);
+                    const float *pp = base + (long long)(s + u) * ld + j0;
+                    v0[u] = pp[0];
+                    v1[u] = pp[1];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
+            }
+            for (; s <= s1; ++s) {
                 const float eta = fmaf((float)s, rr.c, rr.a);
                 const float fl = floorf(eta);
                 const float f = eta - fl;
@@ -86,7 +103,30 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
             const int ld = ydom ? K.ldN : K.ldT;
             const long long slab = ydom ? K.slabN : K.slabT;
             const float *base = img + 2 * ld + 2;
-            for (int s = s0; s <= s1; ++s) {
+            int s = s0;
+            for (; s + 1 <= s1; s += 2) {
+                float v00[2], v01[2], v10[2], v11[2], f[2], h[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float eta = fmaf((float)(s + u), rr.c, rr.a);
+                    const float qz = fmaf((float)(s + u), rz.k, rz.m);
+                    const float zeta = fmaf(vr, qz, z0);
+                    const float fl = floorf(eta), zl = floorf(zeta);
+                    f[u] = eta - fl;
+                    h[u] = zeta - zl;
+                    const int j0 = min(max((int)fl, -2), lim);
+                    const int k0 = min(max((int)zl, -2), K.nz);
+                    const float *pp = base + (long long)(s + u) * slab + (long long)k0 * ld + j0;
+                    v00[u] = pp[0]; v01[u] = pp[1]; v10[u] = pp[ld]; v11[u] = pp[ld + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float lo = fmaf(f[u], v01[u] - v00[u], v00[u]);
+                    const float up = fmaf(f[u], v11[u] - v10[u], v10[u]);
+                    acc += fmaf(h[u], up - lo, lo);
+                }
+            }
+            for (; s <= s1; ++s) {
                 const float eta = fmaf((float)s, rr.c, rr.a);
                 const float qz = fmaf((float)s, rz.k, rz.m);
                 const float zeta = fmaf(vr, qz, z0);
@@ -178,7 +218,7 @@ __device__ inline float reg_curv_sum(const GeoK &K, int i, int j, int k)
 }
 
 template <bool IS3D, int MODE>
-__global__ void __launch_bounds__(256) update_kernel(UpdArgs A)
+__global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
 {
     const GeoK &K = A.k;
     if (MODE == UPD_STEP && A.sc->status) return;
@@ -187,9 +227,8 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs A)
     const int k = blockIdx.z;
     float rho = 1.0f;
     if (MODE == UPD_STEP) rho = (float)A.sc->rho;
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-        const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty + 8 * qq;
+    {
+        const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
         float v = 0.0f;
         if (i < K.nx && j < K.ny) {
             const long long idx = ((long long)k * K.ny + j) * K.nx + i;
@@ -211,16 +250,15 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs A)
                                          : ((long long)j * K.ldN + i + 2);
             A.XN[n_idx] = v;
         }
-        tile[ty + 8 * qq][tx] = v;
+        tile[ty][tx] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-        const int i = blockIdx.x * 32 + ty + 8 * qq, j = blockIdx.y * 32 + tx;
+    {
+        const int i = blockIdx.x * 32 + ty, j = blockIdx.y * 32 + tx;
         if (i < K.nx && j < K.ny) {
             const long long t_idx = IS3D ? ((long long)i * K.slabT + (long long)(k + 2) * K.ldT + j + 2)
                                          : ((long long)i * K.ldT + j + 2);
-            A.XT[t_idx] = tile[tx][ty + 8 * qq];
+            A.XT[t_idx] = tile[tx][ty];
         }
     }
 }
@@ -228,7 +266,7 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs A)
 template <bool IS3D>
 hipError_t upd_dispatch(const UpdArgs &a, int mode, hipStream_t st)
 {
-    dim3 blk(32, 8), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, a.k.nz);
+    dim3 blk(32, 32), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, a.k.nz);
     if (mode == UPD_LAYOUT) hipLaunchKernelGGL((update_kernel<IS3D, UPD_LAYOUT>), grd, blk, 0, st, a);
     else if (mode == UPD_ONES) hipLaunchKernelGGL((update_kernel<IS3D, UPD_ONES>), grd, blk, 0, st, a);
     else hipLaunchKernelGGL((update_kernel<IS3D, UPD_STEP>), grd, blk, 0, st, a);
