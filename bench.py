@@ -111,6 +111,10 @@ def main():
     denom = torch.empty(plan.image_elems, device=dev)
     lalm.lalm_sqs_denom(plan, w, denom)
     beta = cfg["beta"]
+    if beta is None:
+        # workload without a tabulated median: beta from this run's own D_L
+        roi = torch.as_tensor(synth.roi_mask(cfg).reshape(-1), device=dev)
+        beta = synth.configs.BETA_REL * float(denom[roi].median().item())
     delta = synth.configs.delta_mu(cfg)
     state = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
 

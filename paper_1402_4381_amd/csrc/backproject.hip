@@ -153,10 +153,22 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 #pragma unroll
     for (int t = 0; t < KZ; ++t) acc[t] = 0.0f;
 
+    // block-uniform view culling (3D): rays of a view reach slices
+    // zeta in z0 +- zreach * tau +- 1 for in-plane distances tau from the
+    // source; with tau bounded by the block's footprint, views whose cone
+    // misses the block's slices [kb, kb + KZ) are skipped
+    const float bxc = fmaf((float)(blockIdx.x * 32) + 15.5f, K.dx, K.x0);
+    const float byc = fmaf((float)(blockIdx.y * 8) + 3.5f, K.dy, K.y0);
+    const float bhd = sqrtf(256.0f * K.dx * K.dx + 16.0f * K.dy * K.dy) + K.dmax;
     if (inside) {
         const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
         for (int kv = 0; kv < A.nview; ++kv) {
             const ViewRec V = A.views[kv];
+            if (IS3D) {
+                const float tmax = sqrtf((bxc - V.sx) * (bxc - V.sx) + (byc - V.sy) * (byc - V.sy)) + bhd;
+                const float reach = fmaf(K.zreach, tmax, 1.01f);
+                if ((float)kb > V.z0 + reach || (float)(kb + KZ - 1) < V.z0 - reach) continue;
+            }
             const float ddx = X - V.sx, ddy = Y - V.sy;
             const float dc = -(ddx * V.cb + ddy * V.sb);
             const float dp = ddx * V.sb - ddy * V.cb;

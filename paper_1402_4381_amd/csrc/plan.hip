@@ -260,6 +260,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     K.inv_dt = (float)(1.0 / g.dt);
     K.row_center = (float)((nr - 1) / 2.0);
     K.bin_margin = (float)(0.05 + (g.dsd / g.ds) * 4e-6);
+    K.zreach = (float)(((nr - 1) / 2.0 * g.dt) / (g.dsd * g.dz) * 1.0001);
     K.ldT = g.ny + 4;
     K.ldN = g.nx + 4;
     K.slabT = is3d ? (long long)(g.nz + 4) * K.ldT : K.ldT;

@@ -175,11 +175,51 @@ def _sino_chunk(args):
     return _chords(S, u, ph)
 
 
-def analytic_sinogram(cfg, ph, views=None, workers=None):
-    """Noiseless line integrals ``[n_views][n_rows][n_bins]`` (float64)."""
+_CHORDS_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "chords.c")
+_CHORDS_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchords.so")
+_chords_lib = None
+
+
+def build_chords(force=False):
+    """Compile the C version of the chord sums (gcc, OpenMP)."""
+    import subprocess
+    if force or not os.path.exists(_CHORDS_LIB) or \
+            os.path.getmtime(_CHORDS_LIB) < os.path.getmtime(_CHORDS_SRC):
+        tmp = _CHORDS_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               _CHORDS_SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _CHORDS_LIB)
+    return _CHORDS_LIB
+
+
+def _chords_c(cfg, ph, views):
+    global _chords_lib
+    import ctypes
+    if _chords_lib is None:
+        _chords_lib = ctypes.CDLL(build_chords())
+    keys = ("kind", "nx", "ny", "nz", "dx", "dy", "dz", "n_views", "n_views_per_turn",
+            "n_bins", "n_rows", "ds", "dt", "dso", "dsd", "start_angle", "pitch",
+            "channel_offset")
+    geo = np.array([float(cfg[k]) for k in keys])
+    views = np.ascontiguousarray(np.asarray(views, dtype=np.int32))
+    out = np.zeros((len(views), cfg["n_rows"], cfg["n_bins"]))
+    arrs = [np.ascontiguousarray(ph[k], dtype=np.float64) for k in
+            ("cx", "cy", "cz", "ax", "ay", "az", "phi", "amp")]
+    dp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _chords_lib.synth_chords(dp(geo), ctypes.c_int(len(ph["amp"])), *[dp(a) for a in arrs],
+                             ctypes.c_int(1 if ph["is2d"] else 0), dp(views),
+                             ctypes.c_int(len(views)), dp(out))
+    return out
+
+
+def analytic_sinogram(cfg, ph, views=None, workers=None, use_c=True):
+    """Noiseless line integrals ``[n_views][n_rows][n_bins]`` (float64).
+    ``use_c`` selects the compiled chord sums (same formulas as ``_chords``)."""
     if views is None:
         views = np.arange(cfg["n_views"])
     views = np.asarray(views)
+    if use_c:
+        return _chords_c(cfg, ph, views)
     nr, nb = cfg["n_rows"], cfg["n_bins"]
     per = max(1, int(2_000_000 // (nr * nb)))
     chunks = [views[i:i + per] for i in range(0, len(views), per)]
