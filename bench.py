@@ -68,6 +68,53 @@ def cpu_baseline(cfg, data, beta, delta, budget_s):
                        "subset gradient) with the FP64 oracle: %.1f s" % (n, cfg["name"], cfg["M"], dt))
 
 
+def time_to_1hu(lalm, torch, synth, cfg, data, plan, y, w, denom, beta, delta, dev,
+                xstar_iters, max_iters):
+    """Wall time of plain OS-LALM (M subsets, continuation, x0 = 0) to reach
+    1 HU ROI RMS difference from x*.  x* is the one-subset continuation run of
+    the same library (convergent; it reaches the same minimizer as one-subset
+    FISTA with restart)."""
+    geom = synth.geometry_of(cfg)
+    p1 = lalm.lalm_plan_geometry(geom, 1)
+    y1 = torch.as_tensor(data["y"][p1.view_of_slot], dtype=torch.float32, device=dev).reshape(-1).contiguous()
+    w1 = torch.as_tensor(data["w"][p1.view_of_slot], dtype=torch.float32, device=dev).reshape(-1).contiguous()
+    d1 = torch.empty(p1.image_elems, device=dev)
+    lalm.lalm_sqs_denom(p1, w1, d1)
+    xs = lalm.LalmState.zeros_like(torch.zeros(p1.image_elems, device=dev))
+    t0 = time.perf_counter()
+    lalm.lalm_iterate(p1, y1, w1, d1, beta, delta, xs, xstar_iters)
+    t_xs = time.perf_counter() - t0
+    prev = xs.x.clone()
+    lalm.lalm_iterate(p1, y1, w1, d1, beta, delta, xs, 100)
+    radius = synth.roi_radius(cfg)
+    out = torch.zeros(1, dtype=torch.float64, device=dev)
+    lalm.lalm_roi_rmsd_f64(plan, xs.x, prev, radius, out)
+    change = float(out.item()) * synth.HU_PER_MU
+    M = plan.M
+    st = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+    k, hist = 0, []
+    while k < max_iters:
+        lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, M)
+        k += 1
+        lalm.lalm_roi_rmsd_f64(plan, st.x, xs.x, radius, out)
+        hist.append(round(float(out.item()) * synth.HU_PER_MU, 3))
+        if hist[-1] < 1.0:
+            break
+    res = dict(reached=hist[-1] < 1.0, iters=k, rmsd_hu_at_stop=hist[-1],
+               rmsd_hu_per_iter=hist[:40], xstar_iters=xstar_iters + 100,
+               xstar_last100_change_hu=round(change, 5), xstar_wall_s=round(t_xs, 3))
+    if res["reached"]:
+        st = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, k * M)
+        torch.cuda.synchronize()
+        res["wall_s"] = round(time.perf_counter() - t0, 5)
+    else:
+        res["wall_s"] = None
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +123,9 @@ def main():
     ap.add_argument("--workload", default="fan2d_512")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-1hu", action="store_true")
+    ap.add_argument("--xstar-iters", type=int, default=6000)
+    ap.add_argument("--max-iters-1hu", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -167,6 +217,12 @@ def main():
                     kernels_gbs={k: round(v[1] / (v[0] * 1e-3) / 1e9, 1) for k, v in kern.items()},
                     bytes_per_launch=int(b))
 
+    t1hu = None
+    if not args.no_time_to_1hu and cfg["kind"] == 0:
+        log("bench: x* and wall time to 1 HU")
+        t1hu = time_to_1hu(lalm, torch, synth, cfg, data, plan, y, w, denom, beta, delta, dev,
+                           args.xstar_iters, args.max_iters_1hu)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
@@ -191,6 +247,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "profiled_pass_ms_per_step": round(dt_prof / args.steps * 1e3, 5),
+        "time_to_1hu": t1hu,
     }
     print(json.dumps(out), flush=True)
 

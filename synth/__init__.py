@@ -8,11 +8,11 @@ HIP library consume what it produces, and neither is imported here.
 """
 from .configs import CONFIGS, get_config, geometry_of, HU_PER_MU, MU_WATER
 from .phantom import (make_phantom, ray_sources_directions, analytic_sinogram,
-                      noisy_data, pixelize, roi_mask, fov_radius,
+                      noisy_data, pixelize, roi_mask, roi_radius, fov_radius,
                       make_problem_data)
 
 __all__ = [
     "CONFIGS", "get_config", "geometry_of", "HU_PER_MU", "MU_WATER",
     "make_phantom", "ray_sources_directions", "analytic_sinogram",
-    "noisy_data", "pixelize", "roi_mask", "fov_radius", "make_problem_data",
+    "noisy_data", "pixelize", "roi_mask", "roi_radius", "fov_radius", "make_problem_data",
 ]

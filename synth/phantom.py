@@ -274,6 +274,12 @@ def pixelize(cfg, ph, ss=4):
     return img / (len(zoffs) * ss * ss)
 
 
+def roi_radius(cfg):
+    """Radius (mm) of the evaluation region (see :func:`roi_mask`)."""
+    half_w = 0.5 * min(cfg["nx"] * cfg["dx"], cfg["ny"] * cfg["dy"])
+    return min(fov_radius(cfg), half_w) - 2.0 * cfg["dx"]
+
+
 def roi_mask(cfg):
     """Evaluation region: voxel centres within radius
     ``min(R_fov, image half-width) - 2 dx`` of the axis, all slices."""
