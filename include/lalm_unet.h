@@ -1,0 +1,65 @@
+/*
+ * lalm_unet.h -- C ABI of the learned warm start (gfx950, BF16 MFMA).
+ *
+ * Not part of the paper's method: a small 2D U-Net maps an image after a
+ * few OS-LALM iterations to an estimate of the image after many iterations;
+ * plain OS-LALM remains the fallback and the judge (its cost value decides
+ * whether the estimate is kept, and the RMS difference to x* is the figure
+ * of merit).  Architecture (3 levels, 3x3 convolutions + ReLU, 2x2 max
+ * pooling, 2x2 stride-2 transposed convolutions, skip concatenations, 1x1
+ * head, residual output):
+ *   e1a 1->32, e1b 32->32 | pool | e2a 32->64, e2b 64->64 | pool |
+ *   e3a 64->128, e3b 128->128 | up2 128->64, cat e2b | d2a 128->64,
+ *   d2b 64->64 | up1 64->32, cat e1b | d1a 64->32, d1b 32->32 | head 32->1;
+ *   out = x + head(.)
+ * Parameters: one FP32 vector of lalm_unet_param_count() values; for each
+ * layer in the order above its weights then its biases; 3x3 weights
+ * [Cout][3][3][Cin], transposed-conv weights [2][2][Cout][Cin] (output pixel
+ * (2y+a, 2x+b) = W[a][b] . in[y][x] + b), head [Cin] + 1 bias.
+ * Numerics: weights, the input and every stored activation and gradient
+ * tensor in bfloat16 (round to nearest even), MFMA products accumulated in
+ * FP32, loss and parameter gradients in FP32 with FP64 loss sums.
+ * Images are FP32 [batch][H][W] device arrays; H and W multiples of 4.
+ */
+#ifndef LALM_UNET_H
+#define LALM_UNET_H
+
+#include "lalm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lalm_unet lalm_unet;
+
+/* Number of FP32 parameters (465953). */
+LALM_API int64_t lalm_unet_param_count(void);
+
+/* Workspace for batches up to batch_max of height x width images (allocated
+ * here, once).  LALM_E_INVALID for sizes that are not positive multiples of
+ * 4; LALM_E_NOMEM when allocation fails. */
+LALM_API lalm_status lalm_unet_create(int32_t batch_max, int32_t height, int32_t width, lalm_unet **out);
+LALM_API lalm_status lalm_unet_destroy(lalm_unet *net);
+
+/* out = net(x) for batch images (FP32 device arrays [batch][H][W]). */
+LALM_API lalm_status lalm_unet_forward(lalm_unet *net, const float *params, const float *x, float *out,
+                                       int32_t batch, hipStream_t stream);
+
+/* Loss = mean over the mask's pixels (mask: device uint8 [H][W], the same
+ * for every image) of (hu_scale * (net(x) - target))^2; writes the FP32
+ * gradient of the loss w.r.t. params into grad (device, param_count values)
+ * and the loss to loss_dev[0] (device double).  Deterministic. */
+LALM_API lalm_status lalm_unet_loss_grad(lalm_unet *net, const float *params, const float *x,
+                                         const float *target, const uint8_t *mask, double hu_scale,
+                                         int32_t batch, float *grad, double *loss_dev, hipStream_t stream);
+
+/* Adam step t (1-based, bias-corrected; beta1 0.9, beta2 0.999, eps 1e-8)
+ * on FP32 master parameters with moment buffers m, v (device arrays). */
+LALM_API lalm_status lalm_unet_adam(lalm_unet *net, float *params, const float *grad, float *m, float *v,
+                                    int64_t t, double lr, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LALM_UNET_H */

@@ -234,22 +234,22 @@ def loss_and_grad(theta, x, target, mask, hu_scale, bf16=False):
 
     d = conv_back("d1b", a["d1a"], a["d1b"], dA)
     d = conv_back("d1a", a["c1"], a["d1a"], r(d))
-    d = r(d)
-    d_up1, d_e1b_skip = d[..., :32], d[..., 32:]
+    # the transposed conv's output gradient is stored in bfloat16; the skip
+    # part stays at full precision until the pooling path's gradient is added
+    d_up1, d_e1b_skip = r(d[..., :32]), d[..., 32:]
     dx_, dw_, db_ = upconv2_backward(a["d2b"], P["up1"][0], d_up1)
     G["up1"] = (dw_, db_)
     d = conv_back("d2b", a["d2a"], a["d2b"], r(dx_))
     d = conv_back("d2a", a["c2"], a["d2a"], r(d))
-    d = r(d)
-    d_up2, d_e2b_skip = d[..., :64], d[..., 64:]
+    d_up2, d_e2b_skip = r(d[..., :64]), d[..., 64:]
     dx_, dw_, db_ = upconv2_backward(a["e3b"], P["up2"][0], d_up2)
     G["up2"] = (dw_, db_)
     d = conv_back("e3b", a["e3a"], a["e3b"], r(dx_))
     d = conv_back("e3a", a["p2"], a["e3a"], r(d))
-    d_e2b = r(maxpool2_backward(a["e2b"], r(d)) + d_e2b_skip)
+    d_e2b = r(maxpool2_backward(a["e2b"], d) + d_e2b_skip)
     d = conv_back("e2b", a["e2a"], a["e2b"], d_e2b)
     d = conv_back("e2a", a["p1"], a["e2a"], r(d))
-    d_e1b = r(maxpool2_backward(a["e1b"], r(d)) + d_e1b_skip)
+    d_e1b = r(maxpool2_backward(a["e1b"], d) + d_e1b_skip)
     d = conv_back("e1b", a["e1a"], a["e1b"], d_e1b)
     dz = relu_mask(a["e1a"], r(d))
     _, dw, db = conv3x3_backward(a["x"], P["e1a"][0], dz)

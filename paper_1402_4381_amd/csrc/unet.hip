@@ -1,0 +1,1025 @@
+// Learned warm start: a 3-level 2D U-Net on gfx950 with BF16 MFMA
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation).
+//
+// Every convolution-like product is one implicit GEMM kernel, C = A B, with
+// operand gathers chosen by template parameters:
+//   forward 3x3 conv    A(m = pixel, k = tap*Cin + c) = X[pixel + tap][c]
+//                       B(k, n = cout)                = W[cout][tap][c]
+//   input gradient      A(m = pixel, k = tap*Cout + o) = dZ[pixel - tap][o]
+//                       B(k, n = cin)                 = W[o][tap][cin] (pre-transposed)
+//   weight gradient     A(m = cout, k = pixel)        = dZ[pixel][cout]
+//                       B(k, n = tap*Cin + c)         = X[pixel + tap][c]
+//   transposed conv     the same with taps replaced by the 2x2 output phase.
+// Tiles of BM x 32 (A) and BN x 32 (B) bf16 values are staged in LDS (double
+// buffered), four waves each own a 32x32 block of C.  Concatenated inputs are
+// read by channel range from two tensors (no copy).  Epilogues: bias + ReLU +
+// bfloat16 store (forward), FP32 store split by channel range (input
+// gradient), FP32 partial sums per K-split (weight gradient, reduced after in
+// a fixed order: deterministic).  Activations and gradients are NHWC bf16.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lalm_internal.h"
+#include "lalm_unet.h"
+
+namespace unet {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+
+constexpr int BK = 32;
+constexpr int LDK = BK + 8;      // LDS row stride (bf16): 80-byte rows spread the banks
+
+enum { A_CONV = 0, A_UPG = 1, A_MC = 2 };
+enum { B_W = 0, B_NC = 1 };
+enum { E_FWD = 0, E_DG = 1, E_WG = 2 };
+
+struct GemmArgs {
+    int M, N, K;
+    // A operand sources (concatenated by channel: a1 has ac1, a2 has ac2)
+    const bf16 *a1, *a2;
+    int ac1, ac2;
+    int gB, gH, gW;        // pixel grid of the A rows (A_CONV, A_UPG) or of K (A_MC, B_NC)
+    int ntap, tsign;       // A_CONV: 9 or 1 taps, +1 forward / -1 flipped
+    int ab;                // A_MC: >= 0 reads the gradient at the 2x2 output phase ab of a 2x grid
+    // B operand
+    const bf16 *w;         // B_W: [N][K]
+    const bf16 *b1, *b2;   // B_NC sources (concatenated)
+    int bc1, bc2, bntap;
+    // epilogues
+    const float *bias;
+    int relu;
+    bf16 *y;               // E_FWD output (channels N)
+    int yup;               // E_FWD: 1 = store at output phase ab of a 2x grid
+    float *o1, *o2;        // E_DG: n < oc1 -> o1 (ld oc1), else o2 (ld N - oc1)
+    int oc1;
+    float *part;           // E_WG partials [split][M][N]
+    int klen;              // E_WG: K per split (multiple of BK)
+};
+
+__device__ inline void pix_decode(int p, int H, int W, int &b, int &y, int &x)
+{
+    const int hw = H * W;
+    b = p / hw;
+    const int r = p - b * hw;
+    y = r / W;
+    x = r - y * W;
+}
+
+__device__ inline bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (bf16)0.0f;
+    return z;
+}
+
+__device__ inline bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+// 8 consecutive channels c..c+7 of pixel (b, y, x) of a concatenated pair.
+__device__ inline bf16x8 gather_ch(const bf16 *s1, const bf16 *s2, int c1, int c2, int H, int W, int b, int y,
+                                   int x, int c)
+{
+    if (y < 0 || y >= H || x < 0 || x >= W) return zero8();
+    const long long pix = ((long long)b * H + y) * W + x;
+    if (c < c1) return ld8(s1 + pix * c1 + c);
+    return ld8(s2 + pix * c2 + (c - c1));
+}
+
+// A tile (BM rows x BK) -> registers, one bf16x8 per slot
+template <int AMODE, int BM>
+__device__ inline void load_a(const GemmArgs &g, int m0, int k0, int tid, bf16x8 *ra)
+{
+    constexpr int NV = BM * BK / 8 / 256;           // vectors per thread
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int s = tid + v * 256;
+        if (AMODE == A_MC) {
+            // slot -> (pixel kk, channel vector) ; channels along M
+            const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
+            const int k = k0 + kk, m = m0 + mv;
+            bf16x8 r = zero8();
+            if (k < g.K && m < g.M) {
+                int b, y, x;
+                if (g.ab >= 0) {
+                    pix_decode(k, g.gH, g.gW, b, y, x);
+                    const long long pix = ((long long)b * 2 * g.gH + 2 * y + (g.ab >> 1)) * (2 * g.gW) + 2 * x + (g.ab & 1);
+                    r = ld8(g.a1 + pix * g.ac1 + m);
+                } else {
+                    r = ld8(g.a1 + (long long)k * g.ac1 + m);
+                }
+            }
+            ra[v] = r;
+        } else {
+            const int mm = s / (BK / 8), q = (s % (BK / 8)) * 8;
+            const int m = m0 + mm;
+            bf16x8 r = zero8();
+            if (m < g.M) {
+                int b, y, x;
+                pix_decode(m, g.gH, g.gW, b, y, x);
+                if (AMODE == A_CONV) {
+                    const int cin = g.ac1 + g.ac2;
+                    const int tap = k0 / cin, c = k0 - tap * cin + q;
+                    int yy = y, xx = x;
+                    if (g.ntap == 9) {
+                        yy += g.tsign * (tap / 3 - 1);
+                        xx += g.tsign * (tap % 3 - 1);
+                    }
+                    r = gather_ch(g.a1, g.a2, g.ac1, g.ac2, g.gH, g.gW, b, yy, xx, c);
+                } else {   // A_UPG: k = ab*Cs + c over the 2x grid
+                    const int ab = k0 / g.ac1, c = k0 - ab * g.ac1 + q;
+                    const long long pix = ((long long)b * 2 * g.gH + 2 * y + (ab >> 1)) * (2 * g.gW) + 2 * x + (ab & 1);
+                    r = ld8(g.a1 + pix * g.ac1 + c);
+                }
+            }
+            ra[v] = r;
+        }
+    }
+}
+
+template <int AMODE, int BM>
+__device__ inline void store_a(bf16 *As, int tid, const bf16x8 *ra)
+{
+    constexpr int NV = BM * BK / 8 / 256;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int s = tid + v * 256;
+        if (AMODE == A_MC) {
+            const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[(mv + i) * LDK + kk] = ra[v][i];
+        } else {
+            const int mm = s / (BK / 8), q = (s % (BK / 8)) * 8;
+            *reinterpret_cast<bf16x8 *>(As + mm * LDK + q) = ra[v];
+        }
+    }
+}
+
+// B tile (BN x BK) -> registers; BN * BK / 8 vectors spread over the threads
+template <int BMODE, int BN>
+__device__ inline void load_b(const GemmArgs &g, int n0, int k0, int tid, bf16x8 *rb)
+{
+    constexpr int NVT = BN * BK / 8;                // total vectors
+    constexpr int NV = (NVT + 255) / 256;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int s = tid + v * 256;
+        bf16x8 r = zero8();
+        if (s < NVT) {
+            if (BMODE == B_W) {
+                const int nn = s / (BK / 8), q = (s % (BK / 8)) * 8;
+                const int n = n0 + nn;
+                if (n < g.N) r = ld8(g.w + (long long)n * g.K + k0 + q);
+            } else {
+                const int kk = s / (BN / 8), nv = (s % (BN / 8)) * 8;
+                const int k = k0 + kk, n = n0 + nv;
+                if (k < g.K && n < g.N) {
+                    int b, y, x;
+                    pix_decode(k, g.gH, g.gW, b, y, x);
+                    const int cin = g.bc1 + g.bc2;
+                    const int tap = n / cin, c = n - tap * cin;
+                    if (g.bntap == 9) {
+                        y += tap / 3 - 1;
+                        x += tap % 3 - 1;
+                    }
+                    r = gather_ch(g.b1, g.b2, g.bc1, g.bc2, g.gH, g.gW, b, y, x, c);
+                }
+            }
+        }
+        rb[v] = r;
+    }
+}
+
+template <int BMODE, int BN>
+__device__ inline void store_b(bf16 *Bs, int tid, const bf16x8 *rb)
+{
+    constexpr int NVT = BN * BK / 8;
+    constexpr int NV = (NVT + 255) / 256;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int s = tid + v * 256;
+        if (s >= NVT) continue;
+        if (BMODE == B_W) {
+            const int nn = s / (BK / 8), q = (s % (BK / 8)) * 8;
+            *reinterpret_cast<bf16x8 *>(Bs + nn * LDK + q) = rb[v];
+        } else {
+            const int kk = s / (BN / 8), nv = (s % (BN / 8)) * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[(nv + i) * LDK + kk] = rb[v][i];
+        }
+    }
+}
+
+template <int AMODE, int BMODE, int EPI, int BM, int BN>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
+{
+    static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32x32");
+    __shared__ __attribute__((aligned(16))) bf16 As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv % (BM / 32), wn = wv / (BM / 32);
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    int kbeg = 0, kend = g.K;
+    if (EPI == E_WG) {
+        kbeg = blockIdx.z * g.klen;
+        kend = min(g.K, kbeg + g.klen);
+    }
+    constexpr int NVA = BM * BK / 8 / 256;
+    constexpr int NVB = (BN * BK / 8 + 255) / 256;
+    bf16x8 ra[NVA], rb[NVB];
+    floatx16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+
+    int buf = 0;
+    if (kbeg < kend) {
+        load_a<AMODE, BM>(g, m0, kbeg, tid, ra);
+        load_b<BMODE, BN>(g, n0, kbeg, tid, rb);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        store_a<AMODE, BM>(As[buf], tid, ra);
+        store_b<BMODE, BN>(Bs[buf], tid, rb);
+        __syncthreads();
+        if (k0 + BK < kend) {                      // prefetch the next tile
+            load_a<AMODE, BM>(g, m0, k0 + BK, tid, ra);
+            load_b<BMODE, BN>(g, n0, k0 + BK, tid, rb);
+        }
+        const bf16 *as = As[buf] + (wm * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
+        const bf16 *bs = Bs[buf] + (wn * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(as + kk);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(bs + kk);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        buf ^= 1;
+    }
+
+    // element t of acc: row wm*32 + 8(t/4) + 4(lane/32) + t%4, column wn*32 + lane%32
+    const int col = n0 + wn * 32 + (lane & 31);
+    if (EPI == E_FWD) {
+        __syncthreads();
+        bf16 *Cs = As[0];                          // BM x (BN + 8) bf16 staging (fits in 2*BM*LDK)
+        constexpr int LDC = BN + 8;
+        const float bv = (col < g.N && g.bias) ? g.bias[col] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int r = wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+            float v = acc[t] + bv;
+            if (g.relu) v = fmaxf(v, 0.0f);
+            Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
+        }
+        __syncthreads();
+        for (int s = tid; s < BM * (BN / 8); s += 256) {
+            const int r = s / (BN / 8), cv = (s % (BN / 8)) * 8;
+            const int m = m0 + r, n = n0 + cv;
+            if (m >= g.M || n >= g.N) continue;
+            long long pix = m;
+            if (g.yup) {
+                int b, y, x;
+                pix_decode(m, g.gH, g.gW, b, y, x);
+                pix = ((long long)b * 2 * g.gH + 2 * y + (g.ab >> 1)) * (2 * g.gW) + 2 * x + (g.ab & 1);
+            }
+            *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
+        }
+    } else if (EPI == E_DG) {
+        if (col >= g.N) return;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int m = m0 + wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+            if (m >= g.M) continue;
+            if (col < g.oc1) g.o1[(long long)m * g.oc1 + col] = acc[t];
+            else g.o2[(long long)m * (g.N - g.oc1) + (col - g.oc1)] = acc[t];
+        }
+    } else {
+        if (col >= g.N) return;
+        float *dst = g.part + (long long)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int m = m0 + wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+            if (m < g.M) dst[(long long)m * g.N + col] = acc[t];
+        }
+    }
+}
+
+template <int AMODE, int BMODE, int EPI>
+hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
+{
+    if (g.N <= 32) {
+        dim3 grd((g.M + 127) / 128, (g.N + 31) / 32, nsplit);
+        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 128, 32>), grd, dim3(256), 0, st, g);
+    } else {
+        dim3 grd((g.M + 63) / 64, (g.N + 63) / 64, nsplit);
+        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 64, 64>), grd, dim3(256), 0, st, g);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ VALU kernels
+
+// first layer: 3x3 conv 1 -> 32 with ReLU, x FP32 [P] (images), out bf16 [P][32]
+__global__ void conv1_fwd_kernel(const float *x, const float *w, const float *bias, bf16 *out, int B, int H,
+                                 int W)
+{
+    const long long P = (long long)B * H * W;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int b, y, xx;
+    pix_decode((int)p, H, W, b, y, xx);
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
+        float s = 0.0f;
+        if (yy >= 0 && yy < H && xq >= 0 && xq < W) s = (float)(bf16)x[((long long)b * H + yy) * W + xq];
+        v[t] = s;
+    }
+    bf16x8 o[4];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        float a = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a = fmaf((float)(bf16)w[c * 9 + t], v[t], a);
+        a = fmaxf(a + bias[c], 0.0f);
+        o[c >> 3][c & 7] = (bf16)a;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(out + p * 32 + q * 8) = o[q];
+}
+
+// gradient of the first layer's weights and biases: per chunk of pixels,
+// thread o in [0, 320) owns output o = c*10 + t (t < 9 taps, t = 9 bias)
+__global__ void conv1_wgrad_kernel(const float *x, const bf16 *dz, float *part, int B, int H, int W, int chunk)
+{
+    const int o = threadIdx.x;
+    if (o >= 320) return;
+    const int c = o / 10, t = o % 10;
+    const long long P = (long long)B * H * W;
+    const long long p0 = (long long)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+    float acc = 0.0f;
+    for (long long p = p0; p < p1; ++p) {
+        const float d = (float)dz[p * 32 + c];
+        if (d == 0.0f) continue;
+        float v = 1.0f;
+        if (t < 9) {
+            int b, y, xx;
+            pix_decode((int)p, H, W, b, y, xx);
+            const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
+            v = (yy >= 0 && yy < H && xq >= 0 && xq < W) ? (float)(bf16)x[((long long)b * H + yy) * W + xq] : 0.0f;
+        }
+        acc = fmaf(d, v, acc);
+    }
+    part[(long long)blockIdx.x * 320 + o] = acc;
+}
+
+// 2x2 max pooling, NHWC bf16; one thread per output pixel and 8 channels
+__global__ void pool_fwd_kernel(const bf16 *in, bf16 *out, int B, int H, int W, int C)
+{
+    const int Ho = H / 2, Wo = W / 2, CV = C / 8;
+    const long long n = (long long)B * Ho * Wo * CV;
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int cv = (int)(s % CV) * 8;
+    const long long po = s / CV;
+    int b, y, x;
+    pix_decode((int)po, Ho, Wo, b, y, x);
+    const long long base = ((long long)b * H + 2 * y) * W + 2 * x;
+    bf16x8 m = ld8(in + base * C + cv);
+    const long long q[3] = {base + 1, base + W, base + W + 1};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const bf16x8 v = ld8(in + q[k] * C + cv);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if ((float)v[i] > (float)m[i]) m[i] = v[i];
+    }
+    *reinterpret_cast<bf16x8 *>(out + po * C + cv) = m;
+}
+
+// pooling backward: g (FP32, pooled grid) goes to the first maximum of its
+// window in scan order, added into acc (FP32, full grid)
+__global__ void pool_bwd_kernel(const bf16 *in, const float *g, float *acc, int B, int H, int W, int C)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const long long n = (long long)B * Ho * Wo * C;
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int c = (int)(s % C);
+    const long long po = s / C;
+    int b, y, x;
+    pix_decode((int)po, Ho, Wo, b, y, x);
+    const long long base = ((long long)b * H + 2 * y) * W + 2 * x;
+    const long long q[4] = {base, base + 1, base + W, base + W + 1};
+    int best = 0;
+    float mv = (float)in[q[0] * C + c];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        const float v = (float)in[q[k] * C + c];
+        if (v > mv) { mv = v; best = k; }
+    }
+    acc[q[best] * C + c] += g[s];
+}
+
+// dz = bf16(g) where act > 0 (or everywhere when act is null)
+__global__ void mask_to_bf16_kernel(const float *g, const bf16 *act, bf16 *dz, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = (!act || (float)act[i] > 0.0f) ? g[i] : 0.0f;
+    dz[i] = (bf16)v;
+}
+
+// head: out = x + sum_c a[p][c] w[c] + b; with a target also the loss
+// partials and dout = 2 s^2 (out - t) mask / n
+__global__ void head_kernel(const float *x, const bf16 *a, const float *w, const float *bias, float *out,
+                            const float *target, const uint8_t *mask, double s2_over_n, float *dout,
+                            double *lpart, long long P, int HW)
+{
+    __shared__ double red[256];
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    if (p < P) {
+        float acc = bias[0];
+        const bf16 *ap = a + p * 32;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc = fmaf((float)ap[c], (float)(bf16)w[c], acc);
+        const float o = x[p] + acc;
+        if (out) out[p] = o;
+        if (target) {
+            const float mk = mask[p % HW] ? 1.0f : 0.0f;
+            const double e = ((double)o - (double)target[p]) * mk;
+            l = e * e * s2_over_n;
+            dout[p] = (float)(2.0 * s2_over_n * e);
+        }
+    }
+    if (!target) return;
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// head backward: dz_d1b[p][c] = dout[p] w[c] masked by a > 0
+__global__ void head_bwd_kernel(const float *dout, const bf16 *a, const float *w, bf16 *dz, long long P)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P * 32) return;
+    const long long p = s / 32;
+    const int c = (int)(s % 32);
+    const float v = ((float)a[s] > 0.0f) ? dout[p] * (float)(bf16)w[c] : 0.0f;
+    dz[s] = (bf16)v;
+}
+
+// column sums over pixels: part[chunk][c] = sum_{p in chunk} v[p][c]
+// (bf16 v, or FP32 when vf != null); head weight gradient via mul != null:
+// part[chunk][c] = sum_p mul[p] * v[p][c]
+__global__ void colsum_kernel(const bf16 *v, const float *vf, const float *mul, int C, long long P, int chunk,
+                              float *part)
+{
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    const long long p0 = (long long)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+    float acc = 0.0f;
+    for (long long p = p0; p < p1; ++p) {
+        const float x = vf ? vf[p * C + c] : (float)v[p * C + c];
+        acc = mul ? fmaf(mul[p], x, acc) : acc + x;
+    }
+    part[(long long)blockIdx.x * C + c] = acc;
+}
+
+// out[i] = sum_s part[s][i] (fixed order)
+__global__ void reduce_parts_kernel(const float *part, int ns, long long n, float *out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int k = 0; k < ns; ++k) s += part[(long long)k * n + i];
+    out[i] = s;
+}
+
+__global__ void sum_double_kernel(const double *p, int n, double *out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// FP32 master weights -> bf16 forward copy and the pre-transposed
+// input-gradient copies: 3x3 [cin][tap][cout] (the gather applies the
+// negated tap offset), 2x2 [cin][phase][cout]
+__global__ void prep_conv_kernel(const float *w, bf16 *wf, bf16 *wd, int cout, int cin)
+{
+    const long long n = (long long)cout * 9 * cin;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % cin);
+    const int tap = (int)((i / cin) % 9);
+    const int o = (int)(i / (9LL * cin));
+    const bf16 v = (bf16)w[i];
+    wf[i] = v;
+    wd[((long long)c * 9 + tap) * cout + o] = v;
+}
+
+__global__ void prep_up_kernel(const float *w, bf16 *wf, bf16 *wd, int cout, int cin)
+{
+    const long long n = 4LL * cout * cin;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % cin);
+    const int o = (int)((i / cin) % cout);
+    const int ab = (int)(i / ((long long)cout * cin));
+    const bf16 v = (bf16)w[i];
+    wf[i] = v;                                      // [ab][o][c]
+    wd[((long long)c * 4 + ab) * cout + o] = v;     // [c][ab][o]
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, long long n, float lr, float bc1,
+                            float bc2)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+// first layer gradient [c][t] (t < 9 weights, t = 9 bias) -> flat layout
+__global__ void scatter_conv1_kernel(const float *src, float *gw, float *gb)
+{
+    const int o = threadIdx.x;
+    if (o >= 320) return;
+    const int c = o / 10, t = o % 10;
+    if (t < 9) gw[c * 9 + t] = src[o];
+    else gb[c] = src[o];
+}
+
+inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace unet
+
+// ------------------------------------------------------------------ network
+
+using namespace unet;
+
+namespace {
+
+struct LayerDef { const char *name; int kind; int cin, cout; };   // kind 0 conv, 1 up, 2 head
+const LayerDef kLayers[] = {
+    {"e1a", 0, 1, 32}, {"e1b", 0, 32, 32}, {"e2a", 0, 32, 64}, {"e2b", 0, 64, 64},
+    {"e3a", 0, 64, 128}, {"e3b", 0, 128, 128}, {"up2", 1, 128, 64}, {"d2a", 0, 128, 64},
+    {"d2b", 0, 64, 64}, {"up1", 1, 64, 32}, {"d1a", 0, 64, 32}, {"d1b", 0, 32, 32}, {"head", 2, 32, 1}};
+constexpr int kNL = 13;
+enum { E1A, E1B, E2A, E2B, E3A, E3B, UP2, D2A, D2B, UP1, D1A, D1B, HEAD };
+
+int64_t wcount(const LayerDef &l)
+{
+    return l.kind == 0 ? 9LL * l.cin * l.cout : (l.kind == 1 ? 4LL * l.cin * l.cout : l.cin);
+}
+int64_t bcount(const LayerDef &l) { return l.kind == 2 ? 1 : l.cout; }
+
+}  // namespace
+
+struct lalm_unet {
+    int Bmax = 0, H = 0, W = 0;
+    int64_t woff[kNL], boff[kNL], nparam = 0;
+    std::vector<void *> allocs;
+    bf16 *wf[kNL] = {}, *wd[kNL] = {};
+    // activations (bf16 NHWC)
+    bf16 *e1a, *e1b, *p1, *e2a, *e2b, *p2, *e3a, *e3b, *up2, *d2a, *d2b, *up1, *d1a, *d1b;
+    // gradient scratch
+    float *gA, *gB, *gSkip1, *gSkip2, *dout, *part;
+    bf16 *dzA, *dzB;
+    double *lpart;
+    int64_t part_elems = 0;
+    const uint8_t *mask_ptr = nullptr;   // ROI mask whose pixel count is cached
+    long long mask_count = 0;
+};
+
+namespace {
+
+template <class T>
+hipError_t alloc(lalm_unet *n, T **p, size_t count)
+{
+    hipError_t e = hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) n->allocs.push_back((void *)*p);
+    return e;
+}
+
+lalm_status ufail(lalm_status c, const std::string &m)
+{
+    lalm::set_error(m);
+    return c;
+}
+
+#define UCHK(where, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return ufail(LALM_E_HIP, std::string(where) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// forward 3x3 conv (cin >= 32) at grid (B, h, w)
+hipError_t conv_fwd(lalm_unet *n, int L, const bf16 *x1, int c1, const bf16 *x2, int c2, bf16 *y, const float *params,
+                    int B, int h, int w, hipStream_t st)
+{
+    GemmArgs g{};
+    g.M = B * h * w;
+    g.N = kLayers[L].cout;
+    g.K = 9 * (c1 + c2);
+    g.a1 = x1; g.a2 = x2; g.ac1 = c1; g.ac2 = c2;
+    g.gB = B; g.gH = h; g.gW = w;
+    g.ntap = 9; g.tsign = 1; g.ab = -1;
+    g.w = n->wf[L];
+    g.bias = params + n->boff[L];
+    g.relu = 1;
+    g.y = y;
+    return gemm<A_CONV, B_W, E_FWD>(g, 1, st);
+}
+
+hipError_t up_fwd(lalm_unet *n, int L, const bf16 *x, bf16 *y, const float *params, int B, int h, int w,
+                  hipStream_t st)
+{
+    const int cin = kLayers[L].cin, cout = kLayers[L].cout;
+    for (int ab = 0; ab < 4; ++ab) {
+        GemmArgs g{};
+        g.M = B * h * w;
+        g.N = cout;
+        g.K = cin;
+        g.a1 = x; g.ac1 = cin;
+        g.gB = B; g.gH = h; g.gW = w;
+        g.ntap = 1; g.tsign = 1; g.ab = ab;
+        g.w = n->wf[L] + (long long)ab * cout * cin;
+        g.bias = params + n->boff[L];
+        g.relu = 0;
+        g.y = y; g.yup = 1;
+        hipError_t e = gemm<A_CONV, B_W, E_FWD>(g, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// weight gradient of a 3x3 conv: dW[o][tap*cin + c] = sum_p dz[p][o] X[p+tap][c]
+hipError_t conv_wgrad(lalm_unet *n, int L, const bf16 *dz, const bf16 *x1, int c1, const bf16 *x2, int c2,
+                      float *grad, int B, int h, int w, hipStream_t st)
+{
+    GemmArgs g{};
+    g.M = kLayers[L].cout;
+    g.N = 9 * (c1 + c2);
+    g.K = B * h * w;
+    g.a1 = dz; g.ac1 = g.M; g.ab = -1;
+    g.gB = B; g.gH = h; g.gW = w;
+    g.b1 = x1; g.b2 = x2; g.bc1 = c1; g.bc2 = c2; g.bntap = 9;
+    int ns = std::min(64, std::max(1, g.K / 4096));
+    g.klen = ((g.K + ns - 1) / ns + BK - 1) / BK * BK;
+    ns = (g.K + g.klen - 1) / g.klen;
+    g.part = n->part;
+    hipError_t e = gemm<A_MC, B_NC, E_WG>(g, ns, st);
+    if (e != hipSuccess) return e;
+    const long long cnt = (long long)g.M * g.N;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt)), dim3(256), 0, st, n->part, ns, cnt, grad + n->woff[L]);
+    return hipGetLastError();
+}
+
+hipError_t up_wgrad(lalm_unet *n, int L, const bf16 *dz_hi, const bf16 *x, float *grad, int B, int h, int w,
+                    hipStream_t st)
+{
+    const int cin = kLayers[L].cin, cout = kLayers[L].cout;
+    for (int ab = 0; ab < 4; ++ab) {
+        GemmArgs g{};
+        g.M = cout;
+        g.N = cin;
+        g.K = B * h * w;
+        g.a1 = dz_hi; g.ac1 = cout; g.ab = ab;
+        g.gB = B; g.gH = h; g.gW = w;
+        g.b1 = x; g.bc1 = cin; g.bntap = 1;
+        int ns = std::min(64, std::max(1, g.K / 4096));
+        g.klen = ((g.K + ns - 1) / ns + BK - 1) / BK * BK;
+        ns = (g.K + g.klen - 1) / g.klen;
+        g.part = n->part;
+        hipError_t e = gemm<A_MC, B_NC, E_WG>(g, ns, st);
+        if (e != hipSuccess) return e;
+        const long long cnt = (long long)cout * cin;
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt)), dim3(256), 0, st, n->part, ns, cnt,
+                           grad + n->woff[L] + (long long)ab * cnt);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// bias gradient: column sums of dz ([P][C] bf16)
+hipError_t bias_grad(lalm_unet *n, const bf16 *dz, int C, long long P, float *dst, hipStream_t st)
+{
+    const int chunk = 4096;
+    const int ns = (int)((P + chunk - 1) / chunk);
+    hipLaunchKernelGGL(colsum_kernel, dim3(ns), dim3(128), 0, st, dz, (const float *)nullptr,
+                       (const float *)nullptr, C, P, chunk, n->part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(C)), dim3(256), 0, st, n->part, ns, (long long)C, dst);
+    return hipGetLastError();
+}
+
+// input gradient of a 3x3 conv: out[p][c] = sum_{tap, o} dz[p - tap][o] W[o][tap][c]
+hipError_t conv_dgrad(lalm_unet *n, int L, const bf16 *dz, float *o1, int oc1, float *o2, int B, int h, int w,
+                      hipStream_t st)
+{
+    GemmArgs g{};
+    g.M = B * h * w;
+    g.N = kLayers[L].cin;
+    g.K = 9 * kLayers[L].cout;
+    g.a1 = dz; g.ac1 = kLayers[L].cout; g.ac2 = 0;
+    g.gB = B; g.gH = h; g.gW = w;
+    g.ntap = 9; g.tsign = -1; g.ab = -1;
+    g.w = n->wd[L];
+    g.o1 = o1; g.o2 = o2; g.oc1 = oc1;
+    return gemm<A_CONV, B_W, E_DG>(g, 1, st);
+}
+
+// input gradient of a transposed conv: out[p][c] = sum_{ab, o} dz[up(p,ab)][o] W[ab][o][c]
+hipError_t up_dgrad(lalm_unet *n, int L, const bf16 *dz_hi, float *out, int B, int h, int w, hipStream_t st)
+{
+    GemmArgs g{};
+    g.M = B * h * w;
+    g.N = kLayers[L].cin;
+    g.K = 4 * kLayers[L].cout;
+    g.a1 = dz_hi; g.ac1 = kLayers[L].cout;
+    g.gB = B; g.gH = h; g.gW = w;
+    g.ab = -1;
+    g.w = n->wd[L];
+    g.o1 = out; g.oc1 = g.N;
+    return gemm<A_UPG, B_W, E_DG>(g, 1, st);
+}
+
+hipError_t to_dz(const float *gsrc, const bf16 *act, bf16 *dz, long long cnt, hipStream_t st)
+{
+    hipLaunchKernelGGL(mask_to_bf16_kernel, dim3(nblk(cnt)), dim3(256), 0, st, gsrc, act, dz, cnt);
+    return hipGetLastError();
+}
+
+lalm_status prep_weights(lalm_unet *n, const float *params, hipStream_t st)
+{
+    for (int L = 0; L < kNL; ++L) {
+        const LayerDef &l = kLayers[L];
+        if (l.kind == 0 && L != E1A) {
+            hipLaunchKernelGGL(prep_conv_kernel, dim3(nblk(wcount(l))), dim3(256), 0, st, params + n->woff[L], n->wf[L],
+                               n->wd[L], l.cout, l.cin);
+        } else if (l.kind == 1) {
+            hipLaunchKernelGGL(prep_up_kernel, dim3(nblk(wcount(l))), dim3(256), 0, st, params + n->woff[L], n->wf[L],
+                               n->wd[L], l.cout, l.cin);
+        }
+    }
+    UCHK("unet weights", hipGetLastError());
+    return LALM_OK;
+}
+
+lalm_status run_forward(lalm_unet *n, const float *params, const float *x, int B, hipStream_t st)
+{
+    const int H = n->H, W = n->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
+    const long long P = (long long)B * H * W;
+    lalm_status s = prep_weights(n, params, st);
+    if (s != LALM_OK) return s;
+    hipLaunchKernelGGL(conv1_fwd_kernel, dim3(nblk(P)), dim3(256), 0, st, x, params + n->woff[E1A],
+                       params + n->boff[E1A], n->e1a, B, H, W);
+    UCHK("unet e1a", hipGetLastError());
+    UCHK("unet e1b", conv_fwd(n, E1B, n->e1a, 32, nullptr, 0, n->e1b, params, B, H, W, st));
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(nblk(P / 4 * 32 / 8)), dim3(256), 0, st, n->e1b, n->p1, B, H, W, 32);
+    UCHK("unet e2a", conv_fwd(n, E2A, n->p1, 32, nullptr, 0, n->e2a, params, B, H2, W2, st));
+    UCHK("unet e2b", conv_fwd(n, E2B, n->e2a, 64, nullptr, 0, n->e2b, params, B, H2, W2, st));
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(nblk(P / 16 * 64 / 8)), dim3(256), 0, st, n->e2b, n->p2, B, H2, W2, 64);
+    UCHK("unet e3a", conv_fwd(n, E3A, n->p2, 64, nullptr, 0, n->e3a, params, B, H4, W4, st));
+    UCHK("unet e3b", conv_fwd(n, E3B, n->e3a, 128, nullptr, 0, n->e3b, params, B, H4, W4, st));
+    UCHK("unet up2", up_fwd(n, UP2, n->e3b, n->up2, params, B, H4, W4, st));
+    UCHK("unet d2a", conv_fwd(n, D2A, n->up2, 64, n->e2b, 64, n->d2a, params, B, H2, W2, st));
+    UCHK("unet d2b", conv_fwd(n, D2B, n->d2a, 64, nullptr, 0, n->d2b, params, B, H2, W2, st));
+    UCHK("unet up1", up_fwd(n, UP1, n->d2b, n->up1, params, B, H2, W2, st));
+    UCHK("unet d1a", conv_fwd(n, D1A, n->up1, 32, n->e1b, 32, n->d1a, params, B, H, W, st));
+    UCHK("unet d1b", conv_fwd(n, D1B, n->d1a, 32, nullptr, 0, n->d1b, params, B, H, W, st));
+    return LALM_OK;
+}
+
+}  // namespace
+
+extern "C" int64_t lalm_unet_param_count(void)
+{
+    int64_t s = 0;
+    for (int L = 0; L < kNL; ++L) s += wcount(kLayers[L]) + bcount(kLayers[L]);
+    return s;
+}
+
+extern "C" lalm_status lalm_unet_create(int32_t batch_max, int32_t height, int32_t width, lalm_unet **out)
+{
+    if (!out) return ufail(LALM_E_INVALID, "lalm_unet_create: null argument");
+    *out = nullptr;
+    if (batch_max < 1 || height < 4 || width < 4 || height % 4 || width % 4)
+        return ufail(LALM_E_INVALID, "lalm_unet_create: sizes must be positive multiples of 4");
+    if ((long long)batch_max * height * width > (1LL << 30))
+        return ufail(LALM_E_INVALID, "lalm_unet_create: batch too large");
+    lalm_unet *n = new lalm_unet();
+    n->Bmax = batch_max; n->H = height; n->W = width;
+    int64_t o = 0;
+    for (int L = 0; L < kNL; ++L) {
+        n->woff[L] = o;
+        o += wcount(kLayers[L]);
+        n->boff[L] = o;
+        o += bcount(kLayers[L]);
+    }
+    n->nparam = o;
+    const long long P = (long long)batch_max * height * width, P2 = P / 4, P4 = P / 16;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    for (int L = 0; L < kNL; ++L) {
+        if (kLayers[L].kind == 2 || L == E1A) continue;
+        chk(alloc(n, &n->wf[L], (size_t)wcount(kLayers[L])));
+        chk(alloc(n, &n->wd[L], (size_t)wcount(kLayers[L])));
+    }
+    chk(alloc(n, &n->e1a, P * 32)); chk(alloc(n, &n->e1b, P * 32)); chk(alloc(n, &n->p1, P2 * 32));
+    chk(alloc(n, &n->e2a, P2 * 64)); chk(alloc(n, &n->e2b, P2 * 64)); chk(alloc(n, &n->p2, P4 * 64));
+    chk(alloc(n, &n->e3a, P4 * 128)); chk(alloc(n, &n->e3b, P4 * 128)); chk(alloc(n, &n->up2, P2 * 64));
+    chk(alloc(n, &n->d2a, P2 * 64)); chk(alloc(n, &n->d2b, P2 * 64)); chk(alloc(n, &n->up1, P * 32));
+    chk(alloc(n, &n->d1a, P * 32)); chk(alloc(n, &n->d1b, P * 32));
+    chk(alloc(n, &n->gA, P * 64)); chk(alloc(n, &n->gB, P * 64));
+    chk(alloc(n, &n->gSkip1, P * 32)); chk(alloc(n, &n->gSkip2, P2 * 64));
+    chk(alloc(n, &n->dout, P));
+    chk(alloc(n, &n->dzA, P * 64)); chk(alloc(n, &n->dzB, P * 64));
+    chk(alloc(n, &n->lpart, (size_t)(P / 256 + 1)));
+    // partial sums: weight gradients (<= 64 splits x 128 x 1152) and column sums
+    n->part_elems = std::max<int64_t>(64LL * 128 * 1152, (P / 4096 + 1) * 320);
+    chk(alloc(n, &n->part, (size_t)n->part_elems));
+    if (e != hipSuccess) {
+        std::string m = std::string("lalm_unet_create: allocation failed: ") + hipGetErrorString(e);
+        lalm_unet_destroy(n);
+        return ufail(LALM_E_NOMEM, m);
+    }
+    *out = n;
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_unet_destroy(lalm_unet *n)
+{
+    if (!n) return ufail(LALM_E_INVALID, "lalm_unet_destroy: null");
+    (void)hipDeviceSynchronize();
+    for (void *p : n->allocs) (void)hipFree(p);
+    delete n;
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_unet_forward(lalm_unet *n, const float *params, const float *x, float *out,
+                                         int32_t batch, hipStream_t st)
+{
+    if (!n || !params || !x || !out) return ufail(LALM_E_INVALID, "lalm_unet_forward: null argument");
+    if (batch < 1 || batch > n->Bmax) return ufail(LALM_E_INVALID, "lalm_unet_forward: batch out of range");
+    lalm_status s = run_forward(n, params, x, batch, st);
+    if (s != LALM_OK) return s;
+    const long long P = (long long)batch * n->H * n->W;
+    hipLaunchKernelGGL(head_kernel, dim3(nblk(P)), dim3(256), 0, st, x, n->d1b, params + n->woff[HEAD],
+                       params + n->boff[HEAD], out, (const float *)nullptr, (const uint8_t *)nullptr, 0.0,
+                       (float *)nullptr, (double *)nullptr, P, n->H * n->W);
+    UCHK("unet head", hipGetLastError());
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, const float *x, const float *target,
+                                           const uint8_t *mask, double hu_scale, int32_t batch, float *grad,
+                                           double *loss_dev, hipStream_t st)
+{
+    if (!n || !params || !x || !target || !mask || !grad || !loss_dev)
+        return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: null argument");
+    if (batch < 1 || batch > n->Bmax) return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: batch out of range");
+    if (mask != n->mask_ptr) {     // count the mask once per mask buffer
+        std::vector<uint8_t> hm((size_t)n->H * n->W);
+        UCHK("unet mask copy", hipMemcpyAsync(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost, st));
+        UCHK("unet mask sync", hipStreamSynchronize(st));
+        long long cnt = 0;
+        for (uint8_t v : hm) cnt += v ? 1 : 0;
+        n->mask_ptr = mask;
+        n->mask_count = cnt;
+    }
+    const long long nm = n->mask_count;
+    if (nm == 0) return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: empty mask");
+    const int B = batch, H = n->H, W = n->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
+    const long long P = (long long)B * H * W, P2 = P / 4, P4 = P / 16;
+    lalm_status s = run_forward(n, params, x, B, st);
+    if (s != LALM_OK) return s;
+    const double s2n = hu_scale * hu_scale / (double)(nm * B);
+    const unsigned hb = nblk(P);
+    hipLaunchKernelGGL(head_kernel, dim3(hb), dim3(256), 0, st, x, n->d1b, params + n->woff[HEAD],
+                       params + n->boff[HEAD], (float *)nullptr, target, mask, s2n, n->dout, n->lpart, P, H * W);
+    hipLaunchKernelGGL(sum_double_kernel, dim3(1), dim3(256), 0, st, n->lpart, (int)hb, loss_dev);
+    UCHK("unet loss", hipGetLastError());
+
+    // head: weight gradient sum_p dout[p] d1b[p][c], bias sum_p dout[p]
+    {
+        const int chunk = 4096, ns = (int)((P + chunk - 1) / chunk);
+        hipLaunchKernelGGL(colsum_kernel, dim3(ns), dim3(128), 0, st, n->d1b, (const float *)nullptr, n->dout, 32, P,
+                           chunk, n->part);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, n->part, ns, 32LL, grad + n->woff[HEAD]);
+        hipLaunchKernelGGL(colsum_kernel, dim3(ns), dim3(128), 0, st, (const bf16 *)nullptr, n->dout,
+                           (const float *)nullptr, 1, P, chunk, n->part);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, n->part, ns, 1LL, grad + n->boff[HEAD]);
+        hipLaunchKernelGGL(head_bwd_kernel, dim3(nblk(P * 32)), dim3(256), 0, st, n->dout, n->d1b,
+                           params + n->woff[HEAD], n->dzA, P);
+        UCHK("unet head backward", hipGetLastError());
+    }
+    bf16 *dz = n->dzA, *dz2 = n->dzB;
+    // d1b: dz_d1b in dz
+    UCHK("d1b wgrad", conv_wgrad(n, D1B, dz, n->d1a, 32, nullptr, 0, grad, B, H, W, st));
+    UCHK("d1b bgrad", bias_grad(n, dz, 32, P, grad + n->boff[D1B], st));
+    UCHK("d1b dgrad", conv_dgrad(n, D1B, dz, n->gA, 32, nullptr, B, H, W, st));
+    UCHK("d1a dz", to_dz(n->gA, n->d1a, dz2, P * 32, st));
+    std::swap(dz, dz2);
+    // d1a (input = concat[up1, e1b])
+    UCHK("d1a wgrad", conv_wgrad(n, D1A, dz, n->up1, 32, n->e1b, 32, grad, B, H, W, st));
+    UCHK("d1a bgrad", bias_grad(n, dz, 32, P, grad + n->boff[D1A], st));
+    UCHK("d1a dgrad", conv_dgrad(n, D1A, dz, n->gA, 32, n->gSkip1, B, H, W, st));
+    UCHK("up1 dz", to_dz(n->gA, nullptr, dz2, P * 32, st));
+    std::swap(dz, dz2);
+    // up1: input d2b at (H2, W2), output gradient dz at (H, W)
+    UCHK("up1 wgrad", up_wgrad(n, UP1, dz, n->d2b, grad, B, H2, W2, st));
+    UCHK("up1 bgrad", bias_grad(n, dz, 32, P, grad + n->boff[UP1], st));
+    UCHK("up1 dgrad", up_dgrad(n, UP1, dz, n->gA, B, H2, W2, st));
+    UCHK("d2b dz", to_dz(n->gA, n->d2b, dz2, P2 * 64, st));
+    std::swap(dz, dz2);
+    UCHK("d2b wgrad", conv_wgrad(n, D2B, dz, n->d2a, 64, nullptr, 0, grad, B, H2, W2, st));
+    UCHK("d2b bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[D2B], st));
+    UCHK("d2b dgrad", conv_dgrad(n, D2B, dz, n->gA, 64, nullptr, B, H2, W2, st));
+    UCHK("d2a dz", to_dz(n->gA, n->d2a, dz2, P2 * 64, st));
+    std::swap(dz, dz2);
+    UCHK("d2a wgrad", conv_wgrad(n, D2A, dz, n->up2, 64, n->e2b, 64, grad, B, H2, W2, st));
+    UCHK("d2a bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[D2A], st));
+    UCHK("d2a dgrad", conv_dgrad(n, D2A, dz, n->gA, 64, n->gSkip2, B, H2, W2, st));
+    UCHK("up2 dz", to_dz(n->gA, nullptr, dz2, P2 * 64, st));
+    std::swap(dz, dz2);
+    UCHK("up2 wgrad", up_wgrad(n, UP2, dz, n->e3b, grad, B, H4, W4, st));
+    UCHK("up2 bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[UP2], st));
+    UCHK("up2 dgrad", up_dgrad(n, UP2, dz, n->gA, B, H4, W4, st));
+    UCHK("e3b dz", to_dz(n->gA, n->e3b, dz2, P4 * 128, st));
+    std::swap(dz, dz2);
+    UCHK("e3b wgrad", conv_wgrad(n, E3B, dz, n->e3a, 128, nullptr, 0, grad, B, H4, W4, st));
+    UCHK("e3b bgrad", bias_grad(n, dz, 128, P4, grad + n->boff[E3B], st));
+    UCHK("e3b dgrad", conv_dgrad(n, E3B, dz, n->gA, 128, nullptr, B, H4, W4, st));
+    UCHK("e3a dz", to_dz(n->gA, n->e3a, dz2, P4 * 128, st));
+    std::swap(dz, dz2);
+    UCHK("e3a wgrad", conv_wgrad(n, E3A, dz, n->p2, 64, nullptr, 0, grad, B, H4, W4, st));
+    UCHK("e3a bgrad", bias_grad(n, dz, 128, P4, grad + n->boff[E3A], st));
+    UCHK("e3a dgrad", conv_dgrad(n, E3A, dz, n->gA, 64, nullptr, B, H4, W4, st));
+    // pool 2 backward into the skip gradient of e2b, then mask
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(nblk(P4 * 64)), dim3(256), 0, st, n->e2b, n->gA, n->gSkip2, B, H2, W2, 64);
+    UCHK("pool2 backward", hipGetLastError());
+    UCHK("e2b dz", to_dz(n->gSkip2, n->e2b, dz2, P2 * 64, st));
+    std::swap(dz, dz2);
+    UCHK("e2b wgrad", conv_wgrad(n, E2B, dz, n->e2a, 64, nullptr, 0, grad, B, H2, W2, st));
+    UCHK("e2b bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[E2B], st));
+    UCHK("e2b dgrad", conv_dgrad(n, E2B, dz, n->gA, 64, nullptr, B, H2, W2, st));
+    UCHK("e2a dz", to_dz(n->gA, n->e2a, dz2, P2 * 64, st));
+    std::swap(dz, dz2);
+    UCHK("e2a wgrad", conv_wgrad(n, E2A, dz, n->p1, 32, nullptr, 0, grad, B, H2, W2, st));
+    UCHK("e2a bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[E2A], st));
+    UCHK("e2a dgrad", conv_dgrad(n, E2A, dz, n->gA, 32, nullptr, B, H2, W2, st));
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(nblk(P2 * 32)), dim3(256), 0, st, n->e1b, n->gA, n->gSkip1, B, H, W, 32);
+    UCHK("pool1 backward", hipGetLastError());
+    UCHK("e1b dz", to_dz(n->gSkip1, n->e1b, dz2, P * 32, st));
+    std::swap(dz, dz2);
+    UCHK("e1b wgrad", conv_wgrad(n, E1B, dz, n->e1a, 32, nullptr, 0, grad, B, H, W, st));
+    UCHK("e1b bgrad", bias_grad(n, dz, 32, P, grad + n->boff[E1B], st));
+    UCHK("e1b dgrad", conv_dgrad(n, E1B, dz, n->gA, 32, nullptr, B, H, W, st));
+    UCHK("e1a dz", to_dz(n->gA, n->e1a, dz2, P * 32, st));
+    std::swap(dz, dz2);
+    {
+        const int chunk = 4096, ns = (int)((P + chunk - 1) / chunk);
+        hipLaunchKernelGGL(conv1_wgrad_kernel, dim3(ns), dim3(320), 0, st, x, dz, n->part, B, H, W, chunk);
+        // part[s][c*10 + t] -> weights [c][t] (t < 9) and bias [c]
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(320)), dim3(256), 0, st, n->part, ns, 320LL, n->gB);
+        hipLaunchKernelGGL(scatter_conv1_kernel, dim3(1), dim3(320), 0, st, n->gB, grad + n->woff[E1A],
+                           grad + n->boff[E1A]);
+        UCHK("e1a wgrad", hipGetLastError());
+    }
+    return LALM_OK;
+}
+
+extern "C" lalm_status lalm_unet_adam(lalm_unet *n, float *params, const float *grad, float *m, float *v, int64_t t,
+                                      double lr, hipStream_t st)
+{
+    if (!n || !params || !grad || !m || !v || t < 1) return ufail(LALM_E_INVALID, "lalm_unet_adam: bad argument");
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+    hipLaunchKernelGGL(adam_kernel, dim3(nblk(n->nparam)), dim3(256), 0, st, params, grad, m, v, (long long)n->nparam,
+                       (float)lr, bc1, bc2);
+    UCHK("unet adam", hipGetLastError());
+    return LALM_OK;
+}

@@ -23,7 +23,8 @@ EXPORTS = ("lalm_last_error", "lalm_version", "lalm_plan_geometry", "lalm_plan_i
            "lalm_plan_destroy", "lalm_project_subset", "lalm_backproject_subset",
            "lalm_sqs_denom", "lalm_iterate", "lalm_cost_f64", "lalm_dot_f64",
            "lalm_roi_rmsd_f64", "lalm_profile_begin", "lalm_profile_read",
-           "lalm_profile_end")
+           "lalm_profile_end", "lalm_unet_param_count", "lalm_unet_create",
+           "lalm_unet_destroy", "lalm_unet_forward", "lalm_unet_loss_grad", "lalm_unet_adam")
 
 
 class LalmError(RuntimeError):
@@ -87,6 +88,12 @@ def _load():
         "lalm_profile_begin": ([P], I32),
         "lalm_profile_read": ([P, P, P], I32),
         "lalm_profile_end": ([P], I32),
+        "lalm_unet_param_count": ([], I64),
+        "lalm_unet_create": ([I32, I32, I32, ctypes.POINTER(P)], I32),
+        "lalm_unet_destroy": ([P], I32),
+        "lalm_unet_forward": ([P, P, P, P, I32, P], I32),
+        "lalm_unet_loss_grad": ([P, P, P, P, P, F64, I32, P, P, P], I32),
+        "lalm_unet_adam": ([P, P, P, P, P, I64, F64, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -326,3 +333,60 @@ def lalm_profile_read(plan):
 
 def lalm_profile_end(plan):
     _check(_lib.lalm_profile_end(plan.handle))
+
+
+# ---------------------------------------------------------------- warm start
+
+def lalm_unet_param_count():
+    return int(_lib.lalm_unet_param_count())
+
+
+class UNet:
+    """Owner of a ``lalm_unet`` workspace."""
+
+    def __init__(self, handle, batch_max, height, width):
+        self.handle, self.batch_max, self.height, self.width = handle, batch_max, height, width
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                _lib.lalm_unet_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def lalm_unet_create(batch_max, height, width):
+    h = ctypes.c_void_p()
+    _check(_lib.lalm_unet_create(int(batch_max), int(height), int(width), ctypes.byref(h)))
+    return UNet(h, int(batch_max), int(height), int(width))
+
+
+def lalm_unet_destroy(net):
+    if net.handle:
+        _check(_lib.lalm_unet_destroy(net.handle))
+        net.handle = None
+
+
+def lalm_unet_forward(net, params, x, out, batch, stream=None):
+    n = int(batch) * net.height * net.width
+    _check(_lib.lalm_unet_forward(net.handle, _dev(params, "params", numel=lalm_unet_param_count()),
+                                  _dev(x, "x", numel=n), _dev(out, "out", numel=n), int(batch),
+                                  _stream(stream)))
+
+
+def lalm_unet_loss_grad(net, params, x, target, mask, hu_scale, batch, grad, loss, stream=None):
+    n = int(batch) * net.height * net.width
+    P = lalm_unet_param_count()
+    _check(_lib.lalm_unet_loss_grad(net.handle, _dev(params, "params", numel=P), _dev(x, "x", numel=n),
+                                    _dev(target, "target", numel=n),
+                                    _dev(mask, "mask", dtype="uint8", numel=net.height * net.width),
+                                    float(hu_scale), int(batch), _dev(grad, "grad", numel=P),
+                                    _dev(loss, "loss", dtype="float64", numel=1), _stream(stream)))
+
+
+def lalm_unet_adam(net, params, grad, m, v, t, lr, stream=None):
+    P = lalm_unet_param_count()
+    _check(_lib.lalm_unet_adam(net.handle, _dev(params, "params", numel=P), _dev(grad, "grad", numel=P),
+                               _dev(m, "m", numel=P), _dev(v, "v", numel=P), int(t), float(lr),
+                               _stream(stream)))

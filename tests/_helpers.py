@@ -19,7 +19,9 @@ def ensure_built():
 
 
 def header_functions():
-    text = open(HEADER).read()
+    """Every call declared (LALM_API) in include/*.h."""
+    import glob
+    text = "".join(open(p).read() for p in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     return sorted(set(re.findall(r"LALM_API\s+[\w\s\*]*?\b(lalm_\w+)\s*\(", text)))
 
 

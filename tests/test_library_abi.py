@@ -17,8 +17,10 @@ def lib():
     return ctypes.CDLL(LIB)
 
 
-def test_header_is_plain_c():
-    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER])
+def test_headers_are_plain_c():
+    import glob, os
+    for h in sorted(glob.glob(os.path.join(os.path.dirname(HEADER), "*.h"))):
+        subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", h])
 
 
 def test_every_declared_call_is_exported(lib):
@@ -80,3 +82,8 @@ def test_null_arguments_rejected(lib):
     assert L.lalm_dot_f64(None, None, None, 0, None, None) == lalm.LALM_E_INVALID
     assert L.lalm_plan_destroy(None) == lalm.LALM_E_INVALID
     assert lalm.lalm_version().startswith("lalm")
+    assert L.lalm_unet_create(0, 16, 16, None) == lalm.LALM_E_INVALID
+    h = ctypes.c_void_p()
+    assert L.lalm_unet_create(1, 18, 16, ctypes.byref(h)) == lalm.LALM_E_INVALID   # not a multiple of 4
+    from oracle import unet as U
+    assert lalm.lalm_unet_param_count() == U.param_count()
