@@ -11,7 +11,8 @@
  *   e1a 1->32, e1b 32->32 | pool | e2a 32->64, e2b 64->64 | pool |
  *   e3a 64->128, e3b 128->128 | up2 128->64, cat e2b | d2a 128->64,
  *   d2b 64->64 | up1 64->32, cat e1b | d1a 64->32, d1b 32->32 | head 32->1;
- *   out = x + head(.)
+ *   the network sees u = in_scale * x and out = x + head(.) / in_scale
+ *   (in_scale brings images of attenuation values to order one).
  * Parameters: one FP32 vector of lalm_unet_param_count() values; for each
  * layer in the order above its weights then its biases; 3x3 weights
  * [Cout][3][3][Cin], transposed-conv weights [2][2][Cout][Cin] (output pixel
@@ -41,17 +42,19 @@ LALM_API int64_t lalm_unet_param_count(void);
 LALM_API lalm_status lalm_unet_create(int32_t batch_max, int32_t height, int32_t width, lalm_unet **out);
 LALM_API lalm_status lalm_unet_destroy(lalm_unet *net);
 
-/* out = net(x) for batch images (FP32 device arrays [batch][H][W]). */
+/* out = net(x) for batch images (FP32 device arrays [batch][H][W]);
+ * nonneg = 1 clamps the output at zero (the constraint set of the method). */
 LALM_API lalm_status lalm_unet_forward(lalm_unet *net, const float *params, const float *x, float *out,
-                                       int32_t batch, hipStream_t stream);
+                                       int32_t batch, double in_scale, int32_t nonneg, hipStream_t stream);
 
 /* Loss = mean over the mask's pixels (mask: device uint8 [H][W], the same
  * for every image) of (hu_scale * (net(x) - target))^2; writes the FP32
  * gradient of the loss w.r.t. params into grad (device, param_count values)
  * and the loss to loss_dev[0] (device double).  Deterministic. */
 LALM_API lalm_status lalm_unet_loss_grad(lalm_unet *net, const float *params, const float *x,
-                                         const float *target, const uint8_t *mask, double hu_scale,
-                                         int32_t batch, float *grad, double *loss_dev, hipStream_t stream);
+                                         const float *target, const uint8_t *mask, double in_scale,
+                                         double hu_scale, int32_t batch, float *grad, double *loss_dev,
+                                         hipStream_t stream);
 
 /* Adam step t (1-based, bias-corrected; beta1 0.9, beta2 0.999, eps 1e-8)
  * on FP32 master parameters with moment buffers m, v (device arrays). */

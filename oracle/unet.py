@@ -183,11 +183,12 @@ def upconv2_backward(x, w, dy):
 
 # ----------------------------------------------------------------- network
 
-def forward(theta, x, bf16=False):
-    """x: [B, H, W] images.  Returns (output [B, H, W], cache)."""
+def forward(theta, x, bf16=False, in_scale=1.0):
+    """x: [B, H, W] images; the network sees in_scale * x and the output is
+    x + head / in_scale.  Returns (output [B, H, W], cache)."""
     r = bf16_round if bf16 else (lambda a: a)
     P = {k: (r(w), b) for k, (w, b) in unpack(theta).items()}
-    a = {"x": r(x[..., None])}
+    a = {"x": r(in_scale * x[..., None])}
     relu = lambda z: np.maximum(z, 0.0)
     a["e1a"] = r(relu(conv3x3(a["x"], *P["e1a"])))
     a["e1b"] = r(relu(conv3x3(a["e1a"], *P["e1b"])))
@@ -206,20 +207,20 @@ def forward(theta, x, bf16=False):
     a["d1a"] = r(relu(conv3x3(a["c1"], *P["d1a"])))
     a["d1b"] = r(relu(conv3x3(a["d1a"], *P["d1b"])))
     hw, hb = P["head"]
-    out = x + (a["d1b"] @ hw + hb[0])
+    out = x + (a["d1b"] @ hw + hb[0]) / in_scale
     return out, (P, a)
 
 
-def loss_and_grad(theta, x, target, mask, hu_scale, bf16=False):
+def loss_and_grad(theta, x, target, mask, hu_scale, bf16=False, in_scale=1.0):
     """Loss = mean over mask pixels of (hu_scale (out - target))^2, and its
     gradient w.r.t. theta (flat)."""
     r = bf16_round if bf16 else (lambda a: a)
-    out, (P, a) = forward(theta, x, bf16)
+    out, (P, a) = forward(theta, x, bf16, in_scale)
     m = np.broadcast_to(mask, out.shape).astype(np.float64)
     n = m.sum()
     e = (out - target) * m
     loss = float(np.sum((hu_scale * e) ** 2) / n)
-    dout = 2.0 * hu_scale ** 2 * e / n                       # [B, H, W]
+    dout = 2.0 * hu_scale ** 2 * e / n / in_scale            # d loss / d head output
     G = {}
     hw, hb = P["head"]
     G["head"] = (np.einsum("bhwc,bhw->c", a["d1b"], dout), np.array([dout.sum()]))

@@ -95,10 +95,15 @@ __device__ inline bf16x8 gather_ch(const bf16 *s1, const bf16 *s2, int c1, int c
 template <int AMODE, int BM>
 __device__ inline void load_a(const GemmArgs &g, int m0, int k0, int tid, bf16x8 *ra)
 {
-    constexpr int NV = BM * BK / 8 / 256;           // vectors per thread
+    constexpr int NVT = BM * BK / 8;                // vectors in the tile
+    constexpr int NV = (NVT + 255) / 256;           // vectors per thread
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int s = tid + v * 256;
+        if (NVT % 256 != 0 && s >= NVT) {
+            ra[v] = zero8();
+            continue;
+        }
         if (AMODE == A_MC) {
             // slot -> (pixel kk, channel vector) ; channels along M
             const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
@@ -145,10 +150,12 @@ __device__ inline void load_a(const GemmArgs &g, int m0, int k0, int tid, bf16x8
 template <int AMODE, int BM>
 __device__ inline void store_a(bf16 *As, int tid, const bf16x8 *ra)
 {
-    constexpr int NV = BM * BK / 8 / 256;
+    constexpr int NVT = BM * BK / 8;
+    constexpr int NV = (NVT + 255) / 256;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int s = tid + v * 256;
+        if (NVT % 256 != 0 && s >= NVT) continue;
         if (AMODE == A_MC) {
             const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
 #pragma unroll
@@ -229,7 +236,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         kbeg = blockIdx.z * g.klen;
         kend = min(g.K, kbeg + g.klen);
     }
-    constexpr int NVA = BM * BK / 8 / 256;
+    constexpr int NVA = (BM * BK / 8 + 255) / 256;
     constexpr int NVB = (BN * BK / 8 + 255) / 256;
     bf16x8 ra[NVA], rb[NVB];
     floatx16 acc;
@@ -323,8 +330,8 @@ hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
 // ------------------------------------------------------------ VALU kernels
 
 // first layer: 3x3 conv 1 -> 32 with ReLU, x FP32 [P] (images), out bf16 [P][32]
-__global__ void conv1_fwd_kernel(const float *x, const float *w, const float *bias, bf16 *out, int B, int H,
-                                 int W)
+__global__ void conv1_fwd_kernel(const float *x, float in_scale, const float *w, const float *bias, bf16 *out,
+                                 int B, int H, int W)
 {
     const long long P = (long long)B * H * W;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -336,7 +343,7 @@ __global__ void conv1_fwd_kernel(const float *x, const float *w, const float *bi
     for (int t = 0; t < 9; ++t) {
         const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
         float s = 0.0f;
-        if (yy >= 0 && yy < H && xq >= 0 && xq < W) s = (float)(bf16)x[((long long)b * H + yy) * W + xq];
+        if (yy >= 0 && yy < H && xq >= 0 && xq < W) s = (float)(bf16)(in_scale * x[((long long)b * H + yy) * W + xq]);
         v[t] = s;
     }
     bf16x8 o[4];
@@ -352,29 +359,53 @@ __global__ void conv1_fwd_kernel(const float *x, const float *w, const float *bi
     for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(out + p * 32 + q * 8) = o[q];
 }
 
-// gradient of the first layer's weights and biases: per chunk of pixels,
-// thread o in [0, 320) owns output o = c*10 + t (t < 9 taps, t = 9 bias)
-__global__ void conv1_wgrad_kernel(const float *x, const bf16 *dz, float *part, int B, int H, int W, int chunk)
+// gradient of the first layer's weights and biases over a chunk of pixels:
+// part[blk][c*10 + t] = sum_p dz[p][c] * u[p + tap t] (t < 9), bias at t = 9,
+// with u the scaled, bfloat16-rounded input.  256 threads: 4 vectors of 8
+// channels x 64 pixel lanes; the lanes are combined in fixed order.
+__global__ void __launch_bounds__(256) conv1_wgrad_kernel(const float *x, float in_scale, const bf16 *dz,
+                                                          float *part, int B, int H, int W, int chunk)
 {
-    const int o = threadIdx.x;
-    if (o >= 320) return;
-    const int c = o / 10, t = o % 10;
+    __shared__ float red[64 * 32];
+    const int cv = threadIdx.x & 3, pl = threadIdx.x >> 2;
     const long long P = (long long)B * H * W;
     const long long p0 = (long long)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
-    float acc = 0.0f;
-    for (long long p = p0; p < p1; ++p) {
-        const float d = (float)dz[p * 32 + c];
-        if (d == 0.0f) continue;
-        float v = 1.0f;
-        if (t < 9) {
-            int b, y, xx;
-            pix_decode((int)p, H, W, b, y, xx);
+    float acc[8][10];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int t = 0; t < 10; ++t) acc[i][t] = 0.0f;
+    for (long long p = p0 + pl; p < p1; p += 64) {
+        int b, y, xx;
+        pix_decode((int)p, H, W, b, y, xx);
+        float u[10];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
             const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
-            v = (yy >= 0 && yy < H && xq >= 0 && xq < W) ? (float)(bf16)x[((long long)b * H + yy) * W + xq] : 0.0f;
+            u[t] = (yy >= 0 && yy < H && xq >= 0 && xq < W)
+                       ? (float)(bf16)(in_scale * x[((long long)b * H + yy) * W + xq]) : 0.0f;
         }
-        acc = fmaf(d, v, acc);
+        u[9] = 1.0f;
+        const bf16x8 d = ld8(dz + p * 32 + cv * 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float di = (float)d[i];
+#pragma unroll
+            for (int t = 0; t < 10; ++t) acc[i][t] = fmaf(di, u[t], acc[i][t]);
+        }
     }
-    part[(long long)blockIdx.x * 320 + o] = acc;
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[pl * 32 + cv * 8 + i] = acc[i][t];
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            float s = 0.0f;
+            for (int k = 0; k < 64; ++k) s += red[k * 32 + threadIdx.x];
+            part[(long long)blockIdx.x * 320 + threadIdx.x * 10 + t] = s;
+        }
+        __syncthreads();
+    }
 }
 
 // 2x2 max pooling, NHWC bf16; one thread per output pixel and 8 channels
@@ -426,19 +457,32 @@ __global__ void pool_bwd_kernel(const bf16 *in, const float *g, float *acc, int 
 }
 
 // dz = bf16(g) where act > 0 (or everywhere when act is null)
-__global__ void mask_to_bf16_kernel(const float *g, const bf16 *act, bf16 *dz, long long n)
+// dz = bf16(g) where the ReLU was active (act > 0; every element when act
+// is null); 8 elements per thread
+__global__ void mask_to_bf16_kernel(const float *g, const bf16 *act, bf16 *dz, long long n8)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float v = (!act || (float)act[i] > 0.0f) ? g[i] : 0.0f;
-    dz[i] = (bf16)v;
+    if (i >= n8) return;
+    const float4 lo = reinterpret_cast<const float4 *>(g)[2 * i];
+    const float4 hi = reinterpret_cast<const float4 *>(g)[2 * i + 1];
+    const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    bf16x8 o;
+    if (act) {
+        const bf16x8 a = ld8(act + 8 * i);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = (bf16)((float)a[k] > 0.0f ? v[k] : 0.0f);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = (bf16)v[k];
+    }
+    *reinterpret_cast<bf16x8 *>(dz + 8 * i) = o;
 }
 
 // head: out = x + sum_c a[p][c] w[c] + b; with a target also the loss
 // partials and dout = 2 s^2 (out - t) mask / n
-__global__ void head_kernel(const float *x, const bf16 *a, const float *w, const float *bias, float *out,
-                            const float *target, const uint8_t *mask, double s2_over_n, float *dout,
-                            double *lpart, long long P, int HW)
+__global__ void head_kernel(const float *x, float inv_scale, int nonneg, const bf16 *a, const float *w,
+                            const float *bias, float *out, const float *target, const uint8_t *mask,
+                            double s2_over_n, float *dout, double *lpart, long long P, int HW)
 {
     __shared__ double red[256];
     const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -448,13 +492,14 @@ __global__ void head_kernel(const float *x, const bf16 *a, const float *w, const
         const bf16 *ap = a + p * 32;
 #pragma unroll
         for (int c = 0; c < 32; ++c) acc = fmaf((float)ap[c], (float)(bf16)w[c], acc);
-        const float o = x[p] + acc;
-        if (out) out[p] = o;
+        const float o = fmaf(acc, inv_scale, x[p]);
+        if (out) out[p] = nonneg ? fmaxf(o, 0.0f) : o;
         if (target) {
             const float mk = mask[p % HW] ? 1.0f : 0.0f;
             const double e = ((double)o - (double)target[p]) * mk;
             l = e * e * s2_over_n;
-            dout[p] = (float)(2.0 * s2_over_n * e);
+            // gradient w.r.t. the head's output (scaled units)
+            dout[p] = (float)(2.0 * s2_over_n * e * (double)inv_scale);
         }
     }
     if (!target) return;
@@ -478,31 +523,70 @@ __global__ void head_bwd_kernel(const float *dout, const bf16 *a, const float *w
     dz[s] = (bf16)v;
 }
 
-// column sums over pixels: part[chunk][c] = sum_{p in chunk} v[p][c]
-// (bf16 v, or FP32 when vf != null); head weight gradient via mul != null:
-// part[chunk][c] = sum_p mul[p] * v[p][c]
-__global__ void colsum_kernel(const bf16 *v, const float *vf, const float *mul, int C, long long P, int chunk,
-                              float *part)
+// column sums over a chunk of pixels: part[blk][c] = sum_p v[p][c], or
+// sum_p mul[p] v[p][c] when mul is given (v: [P][C] bf16).  256 threads: C/8
+// channel vectors x 2048/C pixel lanes, lanes combined in fixed order.
+template <int C>
+__global__ void __launch_bounds__(256) colsum_kernel(const bf16 *v, const float *mul, long long P, int chunk,
+                                                     float *part)
 {
-    const int c = threadIdx.x;
-    if (c >= C) return;
+    constexpr int CV = C / 8, PL = 256 / CV;
+    __shared__ float red[PL * C];
+    const int cv = threadIdx.x % CV, pl = threadIdx.x / CV;
     const long long p0 = (long long)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
-    float acc = 0.0f;
-    for (long long p = p0; p < p1; ++p) {
-        const float x = vf ? vf[p * C + c] : (float)v[p * C + c];
-        acc = mul ? fmaf(mul[p], x, acc) : acc + x;
+    float acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+    for (long long p = p0 + pl; p < p1; p += PL) {
+        const bf16x8 x = ld8(v + p * C + cv * 8);
+        const float m = mul ? mul[p] : 1.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = fmaf(m, (float)x[i], acc[i]);
     }
-    part[(long long)blockIdx.x * C + c] = acc;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[pl * C + cv * 8 + i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float s = 0.0f;
+        for (int k = 0; k < PL; ++k) s += red[k * C + threadIdx.x];
+        part[(long long)blockIdx.x * C + threadIdx.x] = s;
+    }
 }
 
-// out[i] = sum_s part[s][i] (fixed order)
-__global__ void reduce_parts_kernel(const float *part, int ns, long long n, float *out)
+// part[blk] = sum of v over a chunk (fixed-order tree)
+__global__ void __launch_bounds__(256) sum_chunk_kernel(const float *v, long long P, int chunk, float *part)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float red[256];
+    const long long p0 = (long long)blockIdx.x * chunk, p1 = min(P, p0 + chunk);
     float s = 0.0f;
-    for (int k = 0; k < ns; ++k) s += part[(long long)k * n + i];
-    out[i] = s;
+    for (long long p = p0 + threadIdx.x; p < p1; p += 256) s += v[p];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[i] = sum_s part[s][i] in a fixed order: 32 outputs x 8 split lanes per
+// block (lane j sums splits j, j+8, ...), lanes combined in order
+__global__ void __launch_bounds__(256) reduce_parts_kernel(const float *part, int ns, long long n, float *out)
+{
+    __shared__ float red[8][33];
+    const int ox = threadIdx.x & 31, sy = threadIdx.x >> 5;
+    const long long i = (long long)blockIdx.x * 32 + ox;
+    float s = 0.0f;
+    if (i < n)
+        for (int k = sy; k < ns; k += 8) s += part[(long long)k * n + i];
+    red[sy][ox] = s;
+    __syncthreads();
+    if (sy == 0 && i < n) {
+        float t = red[0][ox];
+#pragma unroll
+        for (int j = 1; j < 8; ++j) t += red[j][ox];
+        out[i] = t;
+    }
 }
 
 __global__ void sum_double_kernel(const double *p, int n, double *out)
@@ -675,6 +759,32 @@ hipError_t up_fwd(lalm_unet *n, int L, const bf16 *x, bf16 *y, const float *para
     return hipSuccess;
 }
 
+// Split-K weight-gradient GEMM (partials [split][M][N]) and the fixed-order
+// reduction of the splits into dst.  Narrow outputs (M <= 32) take 32 x 128
+// tiles; the split count fills the chip (about 2048 blocks) with at least 8
+// K-tiles per split, within the partials buffer.
+hipError_t wgrad_gemm(lalm_unet *n, GemmArgs &g, float *dst, hipStream_t st)
+{
+    const bool narrow = g.M <= 32;
+    const int bm = narrow ? 32 : 64, bn = narrow ? 128 : 64;
+    const int gx = (g.M + bm - 1) / bm, gy = (g.N + bn - 1) / bn;
+    long long ns = (2048 + gx * gy - 1) / (gx * gy);
+    ns = std::min<long long>(ns, std::max(1, g.K / (8 * BK)));
+    ns = std::min<long long>(ns, n->part_elems / ((long long)g.M * g.N));
+    ns = std::max<long long>(ns, 1);
+    g.klen = (int)(((g.K + ns - 1) / ns + BK - 1) / BK * BK);
+    ns = (g.K + g.klen - 1) / g.klen;
+    g.part = n->part;
+    const dim3 grd(gx, gy, (unsigned)ns);
+    if (narrow) hipLaunchKernelGGL((gemm_kernel<A_MC, B_NC, E_WG, 32, 128>), grd, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((gemm_kernel<A_MC, B_NC, E_WG, 64, 64>), grd, dim3(256), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long cnt = (long long)g.M * g.N;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt, 32)), dim3(256), 0, st, n->part, (int)ns, cnt, dst);
+    return hipGetLastError();
+}
+
 // weight gradient of a 3x3 conv: dW[o][tap*cin + c] = sum_p dz[p][o] X[p+tap][c]
 hipError_t conv_wgrad(lalm_unet *n, int L, const bf16 *dz, const bf16 *x1, int c1, const bf16 *x2, int c2,
                       float *grad, int B, int h, int w, hipStream_t st)
@@ -686,15 +796,7 @@ hipError_t conv_wgrad(lalm_unet *n, int L, const bf16 *dz, const bf16 *x1, int c
     g.a1 = dz; g.ac1 = g.M; g.ab = -1;
     g.gB = B; g.gH = h; g.gW = w;
     g.b1 = x1; g.b2 = x2; g.bc1 = c1; g.bc2 = c2; g.bntap = 9;
-    int ns = std::min(64, std::max(1, g.K / 4096));
-    g.klen = ((g.K + ns - 1) / ns + BK - 1) / BK * BK;
-    ns = (g.K + g.klen - 1) / g.klen;
-    g.part = n->part;
-    hipError_t e = gemm<A_MC, B_NC, E_WG>(g, ns, st);
-    if (e != hipSuccess) return e;
-    const long long cnt = (long long)g.M * g.N;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt)), dim3(256), 0, st, n->part, ns, cnt, grad + n->woff[L]);
-    return hipGetLastError();
+    return wgrad_gemm(n, g, grad + n->woff[L], st);
 }
 
 hipError_t up_wgrad(lalm_unet *n, int L, const bf16 *dz_hi, const bf16 *x, float *grad, int B, int h, int w,
@@ -709,29 +811,30 @@ hipError_t up_wgrad(lalm_unet *n, int L, const bf16 *dz_hi, const bf16 *x, float
         g.a1 = dz_hi; g.ac1 = cout; g.ab = ab;
         g.gB = B; g.gH = h; g.gW = w;
         g.b1 = x; g.bc1 = cin; g.bntap = 1;
-        int ns = std::min(64, std::max(1, g.K / 4096));
-        g.klen = ((g.K + ns - 1) / ns + BK - 1) / BK * BK;
-        ns = (g.K + g.klen - 1) / g.klen;
-        g.part = n->part;
-        hipError_t e = gemm<A_MC, B_NC, E_WG>(g, ns, st);
-        if (e != hipSuccess) return e;
-        const long long cnt = (long long)cout * cin;
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt)), dim3(256), 0, st, n->part, ns, cnt,
-                           grad + n->woff[L] + (long long)ab * cnt);
-        e = hipGetLastError();
+        hipError_t e = wgrad_gemm(n, g, grad + n->woff[L] + (long long)ab * cout * cin, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 // bias gradient: column sums of dz ([P][C] bf16)
+hipError_t colsum(const bf16 *v, const float *mul, int C, long long P, int chunk, float *part, hipStream_t st)
+{
+    const unsigned ns = (unsigned)((P + chunk - 1) / chunk);
+    if (C == 32) hipLaunchKernelGGL(colsum_kernel<32>, dim3(ns), dim3(256), 0, st, v, mul, P, chunk, part);
+    else if (C == 64) hipLaunchKernelGGL(colsum_kernel<64>, dim3(ns), dim3(256), 0, st, v, mul, P, chunk, part);
+    else if (C == 128) hipLaunchKernelGGL(colsum_kernel<128>, dim3(ns), dim3(256), 0, st, v, mul, P, chunk, part);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t bias_grad(lalm_unet *n, const bf16 *dz, int C, long long P, float *dst, hipStream_t st)
 {
     const int chunk = 4096;
     const int ns = (int)((P + chunk - 1) / chunk);
-    hipLaunchKernelGGL(colsum_kernel, dim3(ns), dim3(128), 0, st, dz, (const float *)nullptr,
-                       (const float *)nullptr, C, P, chunk, n->part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(C)), dim3(256), 0, st, n->part, ns, (long long)C, dst);
+    hipError_t e = colsum(dz, nullptr, C, P, chunk, n->part, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(C, 32)), dim3(256), 0, st, n->part, ns, (long long)C, dst);
     return hipGetLastError();
 }
 
@@ -768,7 +871,8 @@ hipError_t up_dgrad(lalm_unet *n, int L, const bf16 *dz_hi, float *out, int B, i
 
 hipError_t to_dz(const float *gsrc, const bf16 *act, bf16 *dz, long long cnt, hipStream_t st)
 {
-    hipLaunchKernelGGL(mask_to_bf16_kernel, dim3(nblk(cnt)), dim3(256), 0, st, gsrc, act, dz, cnt);
+    if (cnt % 8) return hipErrorInvalidValue;      // channel counts are multiples of 8
+    hipLaunchKernelGGL(mask_to_bf16_kernel, dim3(nblk(cnt / 8)), dim3(256), 0, st, gsrc, act, dz, cnt / 8);
     return hipGetLastError();
 }
 
@@ -788,13 +892,13 @@ lalm_status prep_weights(lalm_unet *n, const float *params, hipStream_t st)
     return LALM_OK;
 }
 
-lalm_status run_forward(lalm_unet *n, const float *params, const float *x, int B, hipStream_t st)
+lalm_status run_forward(lalm_unet *n, const float *params, const float *x, float in_scale, int B, hipStream_t st)
 {
     const int H = n->H, W = n->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const long long P = (long long)B * H * W;
     lalm_status s = prep_weights(n, params, st);
     if (s != LALM_OK) return s;
-    hipLaunchKernelGGL(conv1_fwd_kernel, dim3(nblk(P)), dim3(256), 0, st, x, params + n->woff[E1A],
+    hipLaunchKernelGGL(conv1_fwd_kernel, dim3(nblk(P)), dim3(256), 0, st, x, in_scale, params + n->woff[E1A],
                        params + n->boff[E1A], n->e1a, B, H, W);
     UCHK("unet e1a", hipGetLastError());
     UCHK("unet e1b", conv_fwd(n, E1B, n->e1a, 32, nullptr, 0, n->e1b, params, B, H, W, st));
@@ -858,8 +962,9 @@ extern "C" lalm_status lalm_unet_create(int32_t batch_max, int32_t height, int32
     chk(alloc(n, &n->dout, P));
     chk(alloc(n, &n->dzA, P * 64)); chk(alloc(n, &n->dzB, P * 64));
     chk(alloc(n, &n->lpart, (size_t)(P / 256 + 1)));
-    // partial sums: weight gradients (<= 64 splits x 128 x 1152) and column sums
-    n->part_elems = std::max<int64_t>(64LL * 128 * 1152, (P / 4096 + 1) * 320);
+    // partial sums: weight-gradient splits (the split count adapts to this
+    // size) and per-chunk column sums
+    n->part_elems = std::max<int64_t>(256LL * 128 * 1152, (P / 4096 + 1) * 320);
     chk(alloc(n, &n->part, (size_t)n->part_elems));
     if (e != hipSuccess) {
         std::string m = std::string("lalm_unet_create: allocation failed: ") + hipGetErrorString(e);
@@ -880,24 +985,26 @@ extern "C" lalm_status lalm_unet_destroy(lalm_unet *n)
 }
 
 extern "C" lalm_status lalm_unet_forward(lalm_unet *n, const float *params, const float *x, float *out,
-                                         int32_t batch, hipStream_t st)
+                                         int32_t batch, double in_scale, int32_t nonneg, hipStream_t st)
 {
     if (!n || !params || !x || !out) return ufail(LALM_E_INVALID, "lalm_unet_forward: null argument");
     if (batch < 1 || batch > n->Bmax) return ufail(LALM_E_INVALID, "lalm_unet_forward: batch out of range");
-    lalm_status s = run_forward(n, params, x, batch, st);
+    if (!(in_scale > 0.0)) return ufail(LALM_E_INVALID, "lalm_unet_forward: in_scale must be positive");
+    lalm_status s = run_forward(n, params, x, (float)in_scale, batch, st);
     if (s != LALM_OK) return s;
     const long long P = (long long)batch * n->H * n->W;
-    hipLaunchKernelGGL(head_kernel, dim3(nblk(P)), dim3(256), 0, st, x, n->d1b, params + n->woff[HEAD],
-                       params + n->boff[HEAD], out, (const float *)nullptr, (const uint8_t *)nullptr, 0.0,
-                       (float *)nullptr, (double *)nullptr, P, n->H * n->W);
+    hipLaunchKernelGGL(head_kernel, dim3(nblk(P)), dim3(256), 0, st, x, (float)(1.0 / in_scale), nonneg ? 1 : 0,
+                       n->d1b, params + n->woff[HEAD], params + n->boff[HEAD], out, (const float *)nullptr,
+                       (const uint8_t *)nullptr, 0.0, (float *)nullptr, (double *)nullptr, P, n->H * n->W);
     UCHK("unet head", hipGetLastError());
     return LALM_OK;
 }
 
 extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, const float *x, const float *target,
-                                           const uint8_t *mask, double hu_scale, int32_t batch, float *grad,
-                                           double *loss_dev, hipStream_t st)
+                                           const uint8_t *mask, double in_scale, double hu_scale, int32_t batch,
+                                           float *grad, double *loss_dev, hipStream_t st)
 {
+    if (!(in_scale > 0.0)) return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: in_scale must be positive");
     if (!n || !params || !x || !target || !mask || !grad || !loss_dev)
         return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: null argument");
     if (batch < 1 || batch > n->Bmax) return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: batch out of range");
@@ -914,23 +1021,22 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     if (nm == 0) return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: empty mask");
     const int B = batch, H = n->H, W = n->W, H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     const long long P = (long long)B * H * W, P2 = P / 4, P4 = P / 16;
-    lalm_status s = run_forward(n, params, x, B, st);
+    lalm_status s = run_forward(n, params, x, (float)in_scale, B, st);
     if (s != LALM_OK) return s;
     const double s2n = hu_scale * hu_scale / (double)(nm * B);
     const unsigned hb = nblk(P);
-    hipLaunchKernelGGL(head_kernel, dim3(hb), dim3(256), 0, st, x, n->d1b, params + n->woff[HEAD],
-                       params + n->boff[HEAD], (float *)nullptr, target, mask, s2n, n->dout, n->lpart, P, H * W);
+    hipLaunchKernelGGL(head_kernel, dim3(hb), dim3(256), 0, st, x, (float)(1.0 / in_scale), 0, n->d1b,
+                       params + n->woff[HEAD], params + n->boff[HEAD], (float *)nullptr, target, mask, s2n, n->dout,
+                       n->lpart, P, H * W);
     hipLaunchKernelGGL(sum_double_kernel, dim3(1), dim3(256), 0, st, n->lpart, (int)hb, loss_dev);
     UCHK("unet loss", hipGetLastError());
 
     // head: weight gradient sum_p dout[p] d1b[p][c], bias sum_p dout[p]
     {
         const int chunk = 4096, ns = (int)((P + chunk - 1) / chunk);
-        hipLaunchKernelGGL(colsum_kernel, dim3(ns), dim3(128), 0, st, n->d1b, (const float *)nullptr, n->dout, 32, P,
-                           chunk, n->part);
+        UCHK("head wgrad", colsum(n->d1b, n->dout, 32, P, chunk, n->part, st));
         hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, n->part, ns, 32LL, grad + n->woff[HEAD]);
-        hipLaunchKernelGGL(colsum_kernel, dim3(ns), dim3(128), 0, st, (const bf16 *)nullptr, n->dout,
-                           (const float *)nullptr, 1, P, chunk, n->part);
+        hipLaunchKernelGGL(sum_chunk_kernel, dim3(ns), dim3(256), 0, st, n->dout, P, chunk, n->part);
         hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, n->part, ns, 1LL, grad + n->boff[HEAD]);
         hipLaunchKernelGGL(head_bwd_kernel, dim3(nblk(P * 32)), dim3(256), 0, st, n->dout, n->d1b,
                            params + n->woff[HEAD], n->dzA, P);
@@ -1002,9 +1108,10 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     std::swap(dz, dz2);
     {
         const int chunk = 4096, ns = (int)((P + chunk - 1) / chunk);
-        hipLaunchKernelGGL(conv1_wgrad_kernel, dim3(ns), dim3(320), 0, st, x, dz, n->part, B, H, W, chunk);
+        hipLaunchKernelGGL(conv1_wgrad_kernel, dim3(ns), dim3(256), 0, st, x, (float)in_scale, dz, n->part, B, H, W,
+                           chunk);
         // part[s][c*10 + t] -> weights [c][t] (t < 9) and bias [c]
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(320)), dim3(256), 0, st, n->part, ns, 320LL, n->gB);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(320, 32)), dim3(256), 0, st, n->part, ns, 320LL, n->gB);
         hipLaunchKernelGGL(scatter_conv1_kernel, dim3(1), dim3(320), 0, st, n->gB, grad + n->woff[E1A],
                            grad + n->boff[E1A]);
         UCHK("e1a wgrad", hipGetLastError());

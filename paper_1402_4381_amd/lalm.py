@@ -91,8 +91,8 @@ def _load():
         "lalm_unet_param_count": ([], I64),
         "lalm_unet_create": ([I32, I32, I32, ctypes.POINTER(P)], I32),
         "lalm_unet_destroy": ([P], I32),
-        "lalm_unet_forward": ([P, P, P, P, I32, P], I32),
-        "lalm_unet_loss_grad": ([P, P, P, P, P, F64, I32, P, P, P], I32),
+        "lalm_unet_forward": ([P, P, P, P, I32, F64, I32, P], I32),
+        "lalm_unet_loss_grad": ([P, P, P, P, P, F64, F64, I32, P, P, P], I32),
         "lalm_unet_adam": ([P, P, P, P, P, I64, F64, P], I32),
     }
     for name, (args, res) in sig.items():
@@ -368,20 +368,21 @@ def lalm_unet_destroy(net):
         net.handle = None
 
 
-def lalm_unet_forward(net, params, x, out, batch, stream=None):
+def lalm_unet_forward(net, params, x, out, batch, in_scale=1.0, nonneg=False, stream=None):
     n = int(batch) * net.height * net.width
     _check(_lib.lalm_unet_forward(net.handle, _dev(params, "params", numel=lalm_unet_param_count()),
                                   _dev(x, "x", numel=n), _dev(out, "out", numel=n), int(batch),
-                                  _stream(stream)))
+                                  float(in_scale), 1 if nonneg else 0, _stream(stream)))
 
 
-def lalm_unet_loss_grad(net, params, x, target, mask, hu_scale, batch, grad, loss, stream=None):
+def lalm_unet_loss_grad(net, params, x, target, mask, hu_scale, batch, grad, loss, in_scale=1.0,
+                        stream=None):
     n = int(batch) * net.height * net.width
     P = lalm_unet_param_count()
     _check(_lib.lalm_unet_loss_grad(net.handle, _dev(params, "params", numel=P), _dev(x, "x", numel=n),
                                     _dev(target, "target", numel=n),
                                     _dev(mask, "mask", dtype="uint8", numel=net.height * net.width),
-                                    float(hu_scale), int(batch), _dev(grad, "grad", numel=P),
+                                    float(in_scale), float(hu_scale), int(batch), _dev(grad, "grad", numel=P),
                                     _dev(loss, "loss", dtype="float64", numel=1), _stream(stream)))
 
 

@@ -1,0 +1,438 @@
+"""Learned warm start for 2D fan-beam OS-LALM (not part of the paper's method).
+
+A small U-Net (the BF16-MFMA kernels of the library) maps the image after
+two OS-LALM iterations to an estimate of the image after fifty.  Everything
+runs through the library's C ABI on one GPU:
+
+* pairs: for each training seed a synthetic scan (seeded phantom, Poisson
+  counts) is reconstructed by the library's own OS-LALM (continuation rho,
+  bit-reversal subset order, x0 = 0); the image after 2 iterations is the
+  input and the one after 50 the target.  Sinograms are synthesised by CPU
+  worker processes while the GPU iterates.
+* training: mean squared error in HU over the reconstruction ROI, Adam with
+  FP32 master weights, cosine learning-rate decay.
+* evaluation on held-out seeds: 2 iterations -> U-Net -> cost guard (the
+  estimate is kept only if its FP64 cost Psi is below that of the 2-iteration
+  image) -> state reset (the aggregate gradients are recomputed at the new
+  image, the continuation counter starts again) -> 10 iterations, against
+  30 plain iterations; RMS difference to x* (one-subset OS-LALM with
+  continuation run to convergence) over the ROI and wall time to 1 HU.
+
+Plain OS-LALM stays the fallback and the judge: the network only proposes a
+starting image and the method's own cost decides whether it is used.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(_HERE, "weights", "unet_fan2d_512.npy")
+
+# Layer table of the network (order, shapes as the C ABI documents them).
+LAYERS = (("e1a", "c3", 1, 32), ("e1b", "c3", 32, 32), ("e2a", "c3", 32, 64), ("e2b", "c3", 64, 64),
+          ("e3a", "c3", 64, 128), ("e3b", "c3", 128, 128), ("up2", "up", 128, 64),
+          ("d2a", "c3", 128, 64), ("d2b", "c3", 64, 64), ("up1", "up", 64, 32),
+          ("d1a", "c3", 64, 32), ("d1b", "c3", 32, 32), ("head", "h", 32, 1))
+# spatial scale of each layer's output (1 = full resolution)
+_LEVEL = dict(e1a=1, e1b=1, e2a=4, e2b=4, e3a=16, e3b=16, up2=4, d2a=4, d2b=4, up1=1, d1a=1, d1b=1, head=1)
+
+
+def layer_shapes():
+    out = []
+    for name, kind, cin, cout in LAYERS:
+        if kind == "c3":
+            out.append((name, (cout, 3, 3, cin), (cout,)))
+        elif kind == "up":
+            out.append((name, (2, 2, cout, cin), (cout,)))
+        else:
+            out.append((name, (cin,), (1,)))
+    return out
+
+
+def init_params(seed=0):
+    """He-normal weights, zero biases, zero head (the network starts as the
+    identity map)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for (name, kind, cin, cout), (_, ws, bs) in zip(LAYERS, layer_shapes()):
+        fan_in = 9 * cin if kind == "c3" else cin
+        w = np.zeros(ws) if kind == "h" else rng.normal(0.0, math.sqrt(2.0 / fan_in), ws)
+        parts += [w.ravel(), np.zeros(int(np.prod(bs)))]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def forward_flops(H, W):
+    """Multiply-adds x 2 of one forward pass over an H x W image."""
+    macs = 0.0
+    for name, kind, cin, cout in LAYERS:
+        px = H * W / _LEVEL[name]
+        macs += px * cout * cin * (9 if kind == "c3" else 1)
+    return 2.0 * macs
+
+
+# ------------------------------------------------------------------ inputs
+
+_WORKER = {}
+
+
+def _worker_init(cfg):
+    _WORKER["cfg"] = cfg
+
+
+def _worker_sino(seed):
+    """Natural-order float32 (y, w) of one synthetic scan (CPU worker)."""
+    import synth
+    d = synth.make_problem_data(_WORKER["cfg"], seed, workers=1)
+    return seed, d["y"].astype(np.float32), d["w"].astype(np.float32)
+
+
+class Problem:
+    """One scan resident on the GPU: subset-major y, w and the SQS denominator."""
+
+    def __init__(self, lalm, torch, plan, y_nat, w_nat, dev):
+        vos = torch.as_tensor(plan.view_of_slot, dtype=torch.long, device=dev)
+        yd = torch.as_tensor(y_nat, device=dev)
+        wd = torch.as_tensor(w_nat, device=dev)
+        self.y = yd.index_select(0, vos).reshape(-1).contiguous()
+        self.w = wd.index_select(0, vos).reshape(-1).contiguous()
+        self.denom = torch.empty(plan.image_elems, device=dev)
+        lalm.lalm_sqs_denom(plan, self.w, self.denom)
+
+
+class Pipeline:
+    def __init__(self, cfg, dev="cuda:0"):
+        import torch
+        import synth
+        from paper_1402_4381_amd import lalm
+        self.torch, self.synth, self.lalm = torch, synth, lalm
+        self.cfg, self.dev = cfg, dev
+        self.M = cfg["M"]
+        self.plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), self.M)
+        self.beta = cfg["beta"]
+        self.delta = synth.configs.delta_mu(cfg)
+        self.H, self.W = cfg["ny"], cfg["nx"]
+        self.in_scale = 1.0 / synth.MU_WATER
+        self.hu = synth.HU_PER_MU
+        self.radius = synth.roi_radius(cfg)
+        self.mask = torch.as_tensor(synth.roi_mask(cfg)[0].astype(np.uint8).reshape(-1), device=dev)
+        self._r = torch.zeros(1, dtype=torch.float64, device=dev)
+        self._c = torch.zeros(3, dtype=torch.float64, device=dev)
+
+    # -------------------------------------------------------------- helpers
+    def zero_state(self):
+        return self.lalm.LalmState.zeros_like(self.torch.zeros(self.plan.image_elems, device=self.dev))
+
+    def iterate(self, prob, state, n_iters):
+        self.lalm.lalm_iterate(self.plan, prob.y, prob.w, prob.denom, self.beta, self.delta, state,
+                               n_iters * self.M)
+
+    def rmsd_hu(self, a, b):
+        self.lalm.lalm_roi_rmsd_f64(self.plan, a, b, self.radius, self._r)
+        return float(self._r.item()) * self.hu
+
+    def cost(self, prob, x):
+        self.lalm.lalm_cost_f64(self.plan, prob.y, prob.w, self.beta, self.delta, x, self._c)
+        return float(self._c[0].item())
+
+    def problem(self, y_nat, w_nat):
+        return Problem(self.lalm, self.torch, self.plan, y_nat, w_nat, self.dev)
+
+    # ---------------------------------------------------------------- pairs
+    def generate_pairs(self, seeds, iters_in, iters_target, pool):
+        torch = self.torch
+        n = len(seeds)
+        X = torch.empty(n, self.H * self.W, device=self.dev)
+        T = torch.empty(n, self.H * self.W, device=self.dev)
+        t0 = time.perf_counter()
+        gpu_s = 0.0
+        for k, (seed, y, w) in enumerate(pool.imap(_worker_sino, seeds, chunksize=1)):
+            g0 = time.perf_counter()
+            prob = self.problem(y, w)
+            st = self.zero_state()
+            self.iterate(prob, st, iters_in)
+            X[k].copy_(st.x)
+            self.iterate(prob, st, iters_target - iters_in)
+            T[k].copy_(st.x)
+            torch.cuda.synchronize()
+            gpu_s += time.perf_counter() - g0
+            if (k + 1) % max(1, n // 20) == 0 or k + 1 == n:
+                print("pairs %d/%d  %.1f s (GPU %.1f s)" % (k + 1, n, time.perf_counter() - t0, gpu_s),
+                      flush=True)
+        return X, T, dict(n=n, wall_s=round(time.perf_counter() - t0, 2), gpu_s=round(gpu_s, 2))
+
+    # ------------------------------------------------------------- training
+    def train(self, X, T, epochs, batch, lr, seed=0, params=None, log_every=50):
+        torch, lalm = self.torch, self.lalm
+        n = X.shape[0]
+        P = lalm.lalm_unet_param_count()
+        net = lalm.lalm_unet_create(batch, self.H, self.W)
+        p = torch.as_tensor(init_params(seed) if params is None else params, device=self.dev).contiguous()
+        m = torch.zeros(P, device=self.dev)
+        v = torch.zeros(P, device=self.dev)
+        grad = torch.zeros(P, device=self.dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        xb = torch.empty(batch, self.H * self.W, device=self.dev)
+        tb = torch.empty(batch, self.H * self.W, device=self.dev)
+        steps_per_epoch = n // batch
+        total = max(1, epochs * steps_per_epoch)
+        rng = np.random.default_rng(seed)
+        hist, k = [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            perm = torch.as_tensor(rng.permutation(n), dtype=torch.long, device=self.dev)
+            acc, cnt = torch.zeros(1, dtype=torch.float64, device=self.dev), 0
+            for s in range(steps_per_epoch):
+                idx = perm[s * batch:(s + 1) * batch]
+                torch.index_select(X, 0, idx, out=xb)
+                torch.index_select(T, 0, idx, out=tb)
+                lalm.lalm_unet_loss_grad(net, p, xb, tb, self.mask, self.hu, batch, grad, loss,
+                                         in_scale=self.in_scale)
+                k += 1
+                lr_k = lr * 0.5 * (1.0 + math.cos(math.pi * (k - 1) / total))
+                lalm.lalm_unet_adam(net, p, grad, m, v, k, lr_k)
+                acc += loss
+                cnt += 1
+                if k % log_every == 0:
+                    print("train step %d/%d  epoch %d  loss(HU^2) %.3f  %.1f s" %
+                          (k, total, ep, float(loss.item()), time.perf_counter() - t0), flush=True)
+            ep_loss = float(acc.item()) / max(cnt, 1)
+            hist.append(round(ep_loss, 4))
+            print("epoch %d  mean loss(HU^2) %.4f  (RMS %.3f HU)  %.1f s" %
+                  (ep, ep_loss, math.sqrt(ep_loss), time.perf_counter() - t0), flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        info = dict(epochs=epochs, batch=batch, lr=lr, steps=k, wall_s=round(wall, 2),
+                    ms_per_step=round(1e3 * wall / max(k, 1), 3), epoch_loss_hu2=hist,
+                    train_tflops=round(3.0 * forward_flops(self.H, self.W) * batch * k / wall / 1e12, 1))
+        return p, info
+
+    # ----------------------------------------------------------- inference
+    def unet_time(self, params, batch=1, reps=20):
+        torch, lalm = self.torch, self.lalm
+        net = lalm.lalm_unet_create(batch, self.H, self.W)
+        x = torch.rand(batch * self.H * self.W, device=self.dev) * 0.02
+        out = torch.empty_like(x)
+        for _ in range(3):
+            lalm.lalm_unet_forward(net, params, x, out, batch, self.in_scale, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lalm.lalm_unet_forward(net, params, x, out, batch, self.in_scale, True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        fl = forward_flops(self.H, self.W) * batch
+        return dict(batch=batch, ms=round(dt * 1e3, 4), gflop=round(fl / 1e9, 2),
+                    tflops=round(fl / dt / 1e12, 1), frac_bf16_peak=round(fl / dt / 2.5e15, 4))
+
+    def warm_start(self, prob, params, net, iters_in, out=None):
+        """iters_in plain iterations, U-Net, cost guard, state reset.
+        Returns (state, kept, psi_in, psi_net, network image)."""
+        torch, lalm = self.torch, self.lalm
+        st = self.zero_state()
+        self.iterate(prob, st, iters_in)
+        xt = torch.empty_like(st.x) if out is None else out
+        lalm.lalm_unet_forward(net, params, st.x, xt, 1, self.in_scale, True)
+        psi_in = self.cost(prob, st.x)
+        psi_net = self.cost(prob, xt)
+        if psi_net < psi_in:
+            # step 0: the next call recomputes the gradients at xt (state reset)
+            st = self.lalm.LalmState(xt.clone(), torch.zeros_like(xt), torch.zeros_like(xt))
+            return st, True, psi_in, psi_net, xt
+        return st, False, psi_in, psi_net, xt
+
+    def x_star(self, prob, x_init, iters):
+        """One-subset OS-LALM with continuation from x_init, run to
+        convergence; returns x* and its change over the last 100 iterations."""
+        torch, lalm, synth = self.torch, self.lalm, self.synth
+        if not hasattr(self, "_p1"):
+            self._p1 = lalm.lalm_plan_geometry(synth.geometry_of(self.cfg), 1)
+        p1 = self._p1
+        # the one-subset plan keeps the natural view order
+        vo = torch.as_tensor(np.argsort(self.plan.view_of_slot), dtype=torch.long, device=self.dev)
+        nr_nb = self.cfg["n_rows"] * self.cfg["n_bins"]
+        sel = torch.as_tensor(p1.view_of_slot, dtype=torch.long, device=self.dev)
+        y1 = prob.y.reshape(-1, nr_nb).index_select(0, vo).index_select(0, sel).reshape(-1).contiguous()
+        w1 = prob.w.reshape(-1, nr_nb).index_select(0, vo).index_select(0, sel).reshape(-1).contiguous()
+        d1 = torch.empty(p1.image_elems, device=self.dev)
+        lalm.lalm_sqs_denom(p1, w1, d1)
+        st = lalm.LalmState(x_init.clone(), torch.zeros_like(x_init), torch.zeros_like(x_init))
+        lalm.lalm_iterate(p1, y1, w1, d1, self.beta, self.delta, st, max(iters - 100, 1))
+        prev = st.x.clone()
+        lalm.lalm_iterate(p1, y1, w1, d1, self.beta, self.delta, st, 100)
+        return st.x, self.rmsd_hu(st.x, prev)
+
+    def evaluate_seed(self, seed, params, net, ws, xstar_iters, max_iters, timing=True):
+        """Held-out comparison on one seed: plain OS-LALM and the warm start,
+        each run up to max_iters iterations in all; RMS difference to x*
+        (ROI, HU) after every iteration, costs, iterations and wall time to
+        1 HU."""
+        synth = self.synth
+        d = synth.make_problem_data(self.cfg, seed)
+        prob = self.problem(d["y"].astype(np.float32), d["w"].astype(np.float32))
+        it_in, it_after, it_plain = ws["iters_in"], ws["iters_after"], ws["iters_plain"]
+        # plain OS-LALM from x0 = 0, one image per iteration
+        st = self.zero_state()
+        plain, psi_plain = [], None
+        for k in range(max_iters):
+            self.iterate(prob, st, 1)
+            plain.append(st.x.clone())
+            if k + 1 == it_plain:
+                psi_plain = self.cost(prob, st.x)
+        xs, xs_change = self.x_star(prob, st.x, xstar_iters)
+        psi_star = self.cost(prob, xs)
+        plain_hu = [self.rmsd_hu(x, xs) for x in plain]
+        del plain
+        # warm start, then plain iterations from the network's image
+        wst, kept, psi_in, psi_net, xt = self.warm_start(prob, params, net, it_in)
+        x_net_hu = self.rmsd_hu(xt, xs)
+        warm_hu, psi_warm = [], None
+        for k in range(max_iters - it_in):
+            self.iterate(prob, wst, 1)
+            warm_hu.append(self.rmsd_hu(wst.x, xs))
+            if k + 1 == it_after:
+                psi_warm = self.cost(prob, wst.x)
+        rel = lambda v: (v - psi_star) / abs(psi_star)
+        res = dict(seed=seed, kept=kept, xstar_last100_change_hu=round(xs_change, 5),
+                   rmsd_hu_after_in=round(plain_hu[it_in - 1], 3), rmsd_hu_unet=round(x_net_hu, 3),
+                   rmsd_hu_warm=[round(v, 3) for v in warm_hu],       # after it_in + 1, it_in + 2, ...
+                   rmsd_hu_plain=[round(v, 3) for v in plain_hu],     # after 1, 2, ...
+                   psi_rel={"in": rel(psi_in), "unet": rel(psi_net), "warm_%d" % (it_in + it_after): rel(psi_warm),
+                            "plain_%d" % it_plain: rel(psi_plain)})
+        k_plain = next((i + 1 for i, v in enumerate(plain_hu) if v < 1.0), None)
+        k_warm = next((i + 1 for i, v in enumerate(warm_hu) if v < 1.0), None)
+        res["iters_to_1hu_plain"] = k_plain
+        res["iters_to_1hu_warm"] = None if k_warm is None else it_in + k_warm
+        if timing:
+            res["wall_s_to_1hu_plain"] = self._time_plain(prob, k_plain) if k_plain else None
+            res["wall_s_to_1hu_warm"] = (self._time_warm(prob, params, net, it_in, k_warm, kept)
+                                         if k_warm else None)
+        return res
+
+    def _time_plain(self, prob, k):
+        torch = self.torch
+        st = self.zero_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.iterate(prob, st, k)
+        torch.cuda.synchronize()
+        return round(time.perf_counter() - t0, 5)
+
+    def _time_warm(self, prob, params, net, it_in, k, kept_expected):
+        torch = self.torch
+        out = torch.empty(self.plan.image_elems, device=self.dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, kept, _, _, _ = self.warm_start(prob, params, net, it_in, out=out)
+        self.iterate(prob, st, k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return round(dt, 5) if kept == kept_expected else None
+
+
+def _summary(rows, ws):
+    """Medians over the evaluated seeds."""
+    it_in, it_after, it_plain = ws["iters_in"], ws["iters_after"], ws["iters_plain"]
+    med = lambda v: None if not v else float(np.median(v))
+    def at(r, key, k):                 # RMSD after k iterations in all
+        if key == "rmsd_hu_plain":
+            return r[key][k - 1]
+        return r["rmsd_hu_unet"] if k == it_in else r[key][k - it_in - 1]
+    k_a = it_in + it_after
+    out = dict(n_seeds=len(rows), kept=sum(r["kept"] for r in rows),
+               median_rmsd_hu_after_in=med([r["rmsd_hu_after_in"] for r in rows]),
+               median_rmsd_hu_unet=med([r["rmsd_hu_unet"] for r in rows]))
+    for k in sorted({k_a, it_plain, 2 * it_plain}):
+        if k <= len(rows[0]["rmsd_hu_plain"]):
+            out["median_rmsd_hu_at_%d" % k] = dict(plain=med([at(r, "rmsd_hu_plain", k) for r in rows]),
+                                                   warm=med([at(r, "rmsd_hu_warm", k) for r in rows]))
+    out["warm_%d_beats_plain_%d" % (k_a, it_plain)] = sum(
+        at(r, "rmsd_hu_warm", k_a) < at(r, "rmsd_hu_plain", it_plain) for r in rows)
+    for key in ("iters_to_1hu_plain", "iters_to_1hu_warm", "wall_s_to_1hu_plain", "wall_s_to_1hu_warm"):
+        v = [r.get(key) for r in rows]
+        out["median_" + key] = med([x for x in v if x is not None])
+        out["reached_" + key] = sum(x is not None for x in v)
+    sp = [r["wall_s_to_1hu_plain"] / r["wall_s_to_1hu_warm"] for r in rows
+          if r.get("wall_s_to_1hu_plain") and r.get("wall_s_to_1hu_warm")]
+    out["median_speedup_to_1hu"] = med(sp)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="U-Net warm start for OS-LALM: pairs, training, evaluation")
+    ap.add_argument("--workload", default="fan2d_512")
+    ap.add_argument("--pairs", type=int, default=4000)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-seeds", type=int, default=20)
+    ap.add_argument("--xstar-iters", type=int, default=6000)
+    ap.add_argument("--max-iters", type=int, default=150, help="iterations per method in the evaluation")
+    ap.add_argument("--workers", type=int, default=14)
+    ap.add_argument("--weights", default=WEIGHTS, help="weights file to write (train) or read (eval only)")
+    ap.add_argument("--eval-only", action="store_true")
+    ap.add_argument("--out", default=None, help="JSON summary path")
+    args = ap.parse_args(argv)
+
+    import multiprocessing as mp
+    import synth
+    cfg = synth.get_config(args.workload)
+    if cfg["kind"] != 0:
+        raise SystemExit("the warm start is 2D (one network per slice image)")
+    ws = dict(synth.configs.UNET_WARMSTART)
+    pool = None
+    if not args.eval_only:
+        # CPU workers are forked before the GPU is touched
+        pool = mp.get_context("fork").Pool(args.workers, initializer=_worker_init, initargs=(cfg,))
+
+    pipe = Pipeline(cfg)
+    torch = pipe.torch
+    report = dict(workload=args.workload, warmstart=ws)
+    if args.eval_only:
+        params = torch.as_tensor(np.load(args.weights), device=pipe.dev).contiguous()
+    else:
+        lo, hi = ws["train_seeds"]
+        seeds = list(range(lo, min(hi, lo + args.pairs)))
+        X, T, info = pipe.generate_pairs(seeds, ws["iters_in"], ws["iters_target"], pool)
+        pool.close()
+        pool.join()
+        report["pairs"] = info
+        params, tinfo = pipe.train(X, T, args.epochs, args.batch, args.lr)
+        report["train"] = tinfo
+        del X, T
+        os.makedirs(os.path.dirname(os.path.abspath(args.weights)), exist_ok=True)
+        np.save(args.weights, params.cpu().numpy())
+        print("weights written to", args.weights, flush=True)
+    report["unet_forward"] = [pipe.unet_time(params, b) for b in (1, 8)]
+    print("unet forward", report["unet_forward"], flush=True)
+    net = pipe.lalm.lalm_unet_create(1, pipe.H, pipe.W)
+    lo, hi = ws["eval_seeds"]
+    rows = []
+    for seed in range(lo, min(hi, lo + args.eval_seeds)):
+        r = pipe.evaluate_seed(seed, params, net, ws, args.xstar_iters, args.max_iters)
+        rows.append(r)
+        print("eval seed %d kept %s  x%d %.2f HU  unet %.2f HU  warm(%d+%d) %.2f HU  plain(%d) %.2f HU  "
+              "to 1 HU: plain %s it %s s, warm %s it %s s  (x* last-100 change %.3f HU)" %
+              (seed, r["kept"], ws["iters_in"], r["rmsd_hu_after_in"], r["rmsd_hu_unet"], ws["iters_in"],
+               ws["iters_after"], r["rmsd_hu_warm"][ws["iters_after"] - 1], ws["iters_plain"],
+               r["rmsd_hu_plain"][ws["iters_plain"] - 1], r["iters_to_1hu_plain"], r.get("wall_s_to_1hu_plain"),
+               r["iters_to_1hu_warm"], r.get("wall_s_to_1hu_warm"), r["xstar_last100_change_hu"]), flush=True)
+    report["eval"] = rows
+    report["eval_settings"] = dict(xstar_iters=args.xstar_iters, max_iters=args.max_iters)
+    report["summary"] = _summary(rows, ws)
+    print(json.dumps(report["summary"]), flush=True)
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        with open(args.out, "w") as f:
+            json.dump(report, f, indent=1)
+    return report
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(_HERE))
+    main()

@@ -6,14 +6,17 @@
  * This is data synthesis, not part of the reconstruction method.
  */
 #include <math.h>
+#include <omp.h>
 
 /* geometry: kind nx ny nz dx dy dz n_views n_views_per_turn n_bins n_rows ds
  *           dt dso dsd start_angle pitch channel_offset (doubles)  */
 void synth_chords(const double *geo, int n_obj, const double *cx, const double *cy,
                   const double *cz, const double *ax, const double *ay, const double *az,
                   const double *phi, const double *amp, int is2d, const int *views, int nv,
-                  double *out)
+                  double *out, int n_threads)
 {
+    /* n_threads <= 0: the OpenMP default */
+    const int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
     const double PI = 3.14159265358979323846;
     int kind = (int)geo[0];
     int n_views = (int)geo[7], vpt = (int)geo[8], nb = (int)geo[9], nr = (int)geo[10];
@@ -21,7 +24,7 @@ void synth_chords(const double *geo, int n_obj, const double *cx, const double *
     double start = geo[15], pitch = geo[16], off = geo[17];
     double feed = (kind == 2) ? pitch * nr * dt * dso / dsd : 0.0;
     long long nray = (long long)nv * nr * nb;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(nt)
     for (long long q = 0; q < nray; ++q) {
         int b = (int)(q % nb);
         int r = (int)((q / nb) % nr);

@@ -98,7 +98,7 @@ DL_MEDIAN = {
     "fan2d_128": 1.152e9,
     "fan2d_512": 1.446e9,
     "cone_axial_512x64": 2.781e10,
-    "cone_helical_512x256": None,
+    "cone_helical_512x256": 1.844e10,
     "tiny2d": 1.188e6,
     "tiny3d": 4.765e5,
     "tiny_helical": 7.325e5,

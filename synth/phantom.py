@@ -192,7 +192,7 @@ def build_chords(force=False):
     return _CHORDS_LIB
 
 
-def _chords_c(cfg, ph, views):
+def _chords_c(cfg, ph, views, n_threads=0):
     global _chords_lib
     import ctypes
     if _chords_lib is None:
@@ -208,18 +208,19 @@ def _chords_c(cfg, ph, views):
     dp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     _chords_lib.synth_chords(dp(geo), ctypes.c_int(len(ph["amp"])), *[dp(a) for a in arrs],
                              ctypes.c_int(1 if ph["is2d"] else 0), dp(views),
-                             ctypes.c_int(len(views)), dp(out))
+                             ctypes.c_int(len(views)), dp(out), ctypes.c_int(int(n_threads)))
     return out
 
 
 def analytic_sinogram(cfg, ph, views=None, workers=None, use_c=True):
     """Noiseless line integrals ``[n_views][n_rows][n_bins]`` (float64).
-    ``use_c`` selects the compiled chord sums (same formulas as ``_chords``)."""
+    ``use_c`` selects the compiled chord sums (same formulas as ``_chords``);
+    ``workers`` is then its thread count (None: the OpenMP default)."""
     if views is None:
         views = np.arange(cfg["n_views"])
     views = np.asarray(views)
     if use_c:
-        return _chords_c(cfg, ph, views)
+        return _chords_c(cfg, ph, views, workers or 0)
     nr, nb = cfg["n_rows"], cfg["n_bins"]
     per = max(1, int(2_000_000 // (nr * nb)))
     chunks = [views[i:i + per] for i in range(0, len(views), per)]

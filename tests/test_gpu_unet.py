@@ -49,10 +49,11 @@ def test_forward_parity(L, B, H, W):
     th = _theta(1)
     rng = np.random.default_rng(2)
     x = rng.uniform(0.0, 1.0, (B, H, W))
-    ref, _ = U.forward(th, x, bf16=True)
+    x = 0.02 * x
+    ref, _ = U.forward(th, x, bf16=True, in_scale=50.0)
     net = L.lalm_unet_create(4, H, W)
     out = torch.empty(B * H * W, device=DEV)
-    L.lalm_unet_forward(net, g32(th), g32(x).reshape(-1), out, B)
+    L.lalm_unet_forward(net, g32(th), g32(x).reshape(-1), out, B, in_scale=50.0)
     got = out.cpu().numpy().reshape(B, H, W).astype(np.float64)
     e = rel_l2(got - x, ref - x)
     say("  correction rel L2 %.2e" % e)
@@ -68,13 +69,13 @@ def test_loss_gradient_parity(L, B, H, W):
     t = x + rng.normal(0, 0.1, x.shape)
     mask = np.ones((H, W), dtype=bool)
     mask[:2, :] = False
-    loss, g, _ = U.loss_and_grad(th, x, t, mask, 5.0, bf16=True)
+    loss, g, _ = U.loss_and_grad(th, x, t, mask, 5.0, bf16=True, in_scale=2.0)
     net = L.lalm_unet_create(B, H, W)
     P = L.lalm_unet_param_count()
     grad = torch.zeros(P, device=DEV)
     lg = torch.zeros(1, dtype=torch.float64, device=DEV)
     L.lalm_unet_loss_grad(net, g32(th), g32(x).reshape(-1), g32(t).reshape(-1),
-                          g32(mask.astype(np.uint8), torch.uint8).reshape(-1), 5.0, B, grad, lg)
+                          g32(mask.astype(np.uint8), torch.uint8).reshape(-1), 5.0, B, grad, lg, in_scale=2.0)
     gl = float(lg.item())
     gg = grad.cpu().numpy().astype(np.float64)
     say("  loss gpu %.8e oracle %.8e" % (gl, loss))
@@ -90,7 +91,7 @@ def test_loss_gradient_parity(L, B, H, W):
     # deterministic
     grad2 = torch.zeros(P, device=DEV)
     L.lalm_unet_loss_grad(net, g32(th), g32(x).reshape(-1), g32(t).reshape(-1),
-                          g32(mask.astype(np.uint8), torch.uint8).reshape(-1), 5.0, B, grad2, lg)
+                          g32(mask.astype(np.uint8), torch.uint8).reshape(-1), 5.0, B, grad2, lg, in_scale=2.0)
     assert torch.equal(grad, grad2)
 
 

@@ -78,7 +78,7 @@ def test_gradient_matches_finite_differences():
     t = x + rng.normal(0, 0.1, x.shape)
     mask = np.ones((8, 8), dtype=bool)
     mask[0, :] = False
-    loss, g, _ = U.loss_and_grad(th, x, t, mask, 3.0)
+    loss, g, _ = U.loss_and_grad(th, x, t, mask, 3.0, in_scale=1.7)
     idx = rng.choice(len(th), 40, replace=False)
     # also every layer's first weight and bias
     o = 0
@@ -90,7 +90,8 @@ def test_gradient_matches_finite_differences():
     for k in idx:
         tp = th.copy(); tp[k] += h
         tm = th.copy(); tm[k] -= h
-        fd = (U.loss_and_grad(tp, x, t, mask, 3.0)[0] - U.loss_and_grad(tm, x, t, mask, 3.0)[0]) / (2 * h)
+        fd = (U.loss_and_grad(tp, x, t, mask, 3.0, in_scale=1.7)[0]
+              - U.loss_and_grad(tm, x, t, mask, 3.0, in_scale=1.7)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-5 * max(1.0, abs(g[k])) + 1e-7, (k, fd, g[k])
 
 
@@ -106,3 +107,25 @@ def test_adam_step_reduces_loss():
         _, g, _ = U.loss_and_grad(th, x, t, mask, 10.0)
         th, m, v = U.adam_step(th, g, m, v, k, 1e-3)
     assert U.loss_and_grad(th, x, t, mask, 10.0)[0] < 0.5 * l0
+
+
+def test_warmstart_layer_table_matches_the_oracle():
+    """The pipeline's parameter layout (init, FLOP count) agrees with the
+    oracle network's: same layers, shapes and order; the initial network is
+    the identity (zero head)."""
+    from paper_1402_4381_amd import warmstart as W
+    a = [(n, tuple(w), tuple(b)) for n, w, b in W.layer_shapes()]
+    b = [(n, tuple(w), tuple(bb)) for n, w, bb in U.param_shapes()]
+    assert a == b
+    th = W.init_params(3)
+    assert th.size == U.param_count()
+    x = np.random.default_rng(0).uniform(0, 0.03, (1, 8, 8))
+    out, _ = U.forward(th.astype(np.float64), x, in_scale=50.0)
+    assert np.array_equal(out, x)
+    # FLOPs: 2 x (weights of each layer) x (pixels at its resolution)
+    H = W_ = 16
+    res = dict(e1a=1, e1b=1, e2a=4, e2b=4, e3a=16, e3b=16, up2=4, d2a=4, d2b=4, up1=1, d1a=1, d1b=1,
+               head=1)
+    f = sum(2 * np.prod(ws) * H * W_ / res[n] / (4 if n.startswith("up") else 1)
+            for n, ws, _ in U.param_shapes())
+    assert W.forward_flops(H, W_) == pytest.approx(f)
