@@ -239,6 +239,26 @@ double og_weight(const og_geom *g, int v, int r, int b, int i, int j, int k)
     return w * L;
 }
 
+/* Selected entries of A' sino: out[n] = sum over the rays of the listed
+ * views of a(ray, voxel n) * sino(ray), each entry summed on its own in ray
+ * order (voxel n = (k, j, i) = vox[3n .. 3n+2]). */
+void og_back_at(const og_geom *g, const double *sino, const int *views, int nv, const int *vox, int nvox,
+                double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int n = 0; n < nvox; ++n) {
+        const int k = vox[3 * n], j = vox[3 * n + 1], i = vox[3 * n + 2];
+        double acc = 0.0;
+        for (int kv = 0; kv < nv; ++kv)
+            for (int r = 0; r < g->n_rows; ++r)
+                for (int b = 0; b < g->n_bins; ++b) {
+                    const double s = sino[((long long)kv * g->n_rows + r) * g->n_bins + b];
+                    if (s != 0.0) acc += og_weight(g, views[kv], r, b, i, j, k) * s;
+                }
+        out[n] = acc;
+    }
+}
+
 /* Dense A for tiny geometries: A[(kv, r, b)][(k, j, i)]. */
 void og_dense(const og_geom *g, const int *views, int nv, double *A)
 {

@@ -83,6 +83,7 @@ def _L():
         _lib.og_dense.argtypes = [gp, ip, ctypes.c_int, dp]
         _lib.og_count_samples.argtypes = [gp, ip, ctypes.c_int]
         _lib.og_count_samples.restype = ctypes.c_longlong
+        _lib.og_back_at.argtypes = [gp, dp, ip, ctypes.c_int, ip, ctypes.c_int, dp]
     return _lib
 
 
@@ -164,6 +165,17 @@ def back_at(cfg, sino, views, voxels):
                         if wgt != 0.0:
                             acc += wgt * sino[kv, r, b]
         out[n] = acc
+    return out
+
+
+def back_at_c(cfg, sino, views, voxels):
+    """:func:`back_at` in C (the same sums, OpenMP over the entries): fast
+    enough for sampled entries of full-size geometries."""
+    views = _views(cfg, views)
+    sino = np.ascontiguousarray(sino, dtype=np.float64).reshape(len(views), cfg["n_rows"], cfg["n_bins"])
+    vox = np.ascontiguousarray(np.asarray(voxels, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros(len(vox))
+    _L().og_back_at(ctypes.byref(_geom(cfg)), _dp(sino), _ip(views), len(views), _ip(vox), len(vox), _dp(out))
     return out
 
 

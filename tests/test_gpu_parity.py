@@ -239,6 +239,70 @@ def test_os_lalm_parity_fan2d_512(L):
     assert d <= 0.5
 
 
+@pytest.mark.parametrize("name,over,M,n_iter", [("cone_axial_512x64", MED3D, 5, 4),
+                                                ("cone_helical_512x256", MEDHEL, 6, 3)])
+def test_os_lalm_parity_3d(L, name, over, M, n_iter):
+    """Free-running OS-LALM on medium 3D geometries (26-neighbour
+    regularizer, cone-beam projector pair), beta from the problem's own D_L."""
+    cfg = synth.get_config(name, **over)
+    data = _problem(cfg)
+    dl = ora.sqs_denom(cfg, data["w"])
+    cfg["beta"] = synth.configs.BETA_REL * float(np.median(dl[synth.roi_mask(cfg)]))
+    data, ref, plan, prob, st, stats = _run_both(L, cfg, M, n_iter)
+    d, mism, rs, xi = _report(cfg, ref, st, stats)
+    size = ora.rmsd_hu(ref["x"], np.zeros_like(ref["x"]), synth.roi_mask(cfg), synth.HU_PER_MU)
+    say("%s (medium) free-running: RMSD %.2e HU (image RMS %.0f HU), restart mismatches %d / %d"
+        % (name, d, size, mism, len(rs)))
+    assert size > 100.0
+    assert d <= 0.5
+
+
+# full-size workloads with the subset counts the benchmark runs them with
+FULL = [("fan2d_512", 24, 20), ("cone_axial_512x64", 12, 20), ("cone_helical_512x256", 12, 12)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,M,n_vox", FULL)
+def test_full_size_sampled_parity(L, name, M, n_vox):
+    """Full-size geometry in the benchmark's launch configuration: sampled
+    rays of A_m x against the oracle's ray integrals, sampled voxels of
+    A_m' r against the oracle's per-entry sums (same FP32-rounded inputs)."""
+    cfg = synth.get_config(name)
+    say("full-size sampled parity", name, "M", M)
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    shape = ora.image_shape(cfg)
+    rng = np.random.default_rng(11)
+    x32 = rng.uniform(0.0, 0.03, shape).astype(np.float32)
+    xo = x32.astype(np.float64)
+    m = int(plan.order[1])                       # the subset the first step projects
+    n = plan.subset_rays(m)
+    views = plan.subset_views(m)
+    nr, nb = cfg["n_rows"], cfg["n_bins"]
+    out = torch.empty(n, device=DEV)
+    L.lalm_project_subset(plan, m, gpu(x32).reshape(-1), out)
+    torch.cuda.synchronize()
+    q = np.concatenate([rng.choice(n, 200, replace=False),
+                        [0, nb - 1, nr * nb - 1, n - nb, n - 1, (n // 2) // nb * nb]])
+    got = out.cpu().numpy()[q].astype(np.float64)
+    ref = np.array([ora.ray_integral(cfg, xo, int(views[k // (nr * nb)]), int((k // nb) % nr), int(k % nb))
+                    for k in q])
+    efp = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  A_m x: %d rays, max err / max %.2e" % (len(q), efp))
+    assert efp <= 1e-5
+    r32 = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    xb = torch.empty(plan.image_elems, device=DEV)
+    L.lalm_backproject_subset(plan, m, gpu(r32), xb)
+    torch.cuda.synchronize()
+    nz, ny, nx = shape
+    vox = [(nz // 2, ny // 2, nx // 2), (0, ny // 2, 0), (nz - 1, ny // 3, nx - 1), (0, 0, 0)]
+    vox += [tuple(int(rng.integers(0, d)) for d in shape) for _ in range(n_vox - len(vox))]
+    gotb = xb.cpu().numpy().reshape(shape)[tuple(np.array(vox).T)].astype(np.float64)
+    refb = ora.back_at_c(cfg, r32.astype(np.float64).reshape(len(views), nr, nb), views, vox)
+    ebp = np.abs(gotb - refb).max() / np.abs(refb).max()
+    say("  A_m' r: %d voxels, max err / max %.2e" % (len(vox), ebp))
+    assert ebp <= 1e-5
+
+
 def test_fixed_rho_parity(L):
     cfg = synth.get_config("fan2d_128")
     data, ref, plan, prob, st, stats = _run_both(L, cfg, 4, 10, continuation=False, rho_fixed=0.1)
