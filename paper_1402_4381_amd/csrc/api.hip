@@ -81,7 +81,7 @@ extern "C" lalm_status lalm_project_subset(lalm_plan *p, int32_t m, const float 
     if (!p || !x || !out_sub) return fail(LALM_E_INVALID, "lalm_project_subset: null argument");
     if (m < 0 || m >= p->M) return fail(LALM_E_INVALID, "lalm_project_subset: subset out of range");
     HIPCHK("project layout", launch_update(p, UPD_LAYOUT, const_cast<float *>(x), nullptr, nullptr,
-                                           nullptr, 0.0f, 0, st));
+                                           nullptr, 0.0f, 0, nullptr, st));
     HIPCHK("project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), y_sub, w_sub, out_sub, 0, 0,
                                 nullptr, 0, st));
     return LALM_OK;
@@ -103,7 +103,7 @@ extern "C" lalm_status lalm_backproject_subset(lalm_plan *p, int32_t m, const fl
 extern "C" lalm_status lalm_sqs_denom(lalm_plan *p, const float *w_full, float *denom, hipStream_t st)
 {
     if (!p || !w_full || !denom) return fail(LALM_E_INVALID, "lalm_sqs_denom: null argument");
-    HIPCHK("sqs ones", launch_update(p, UPD_ONES, nullptr, nullptr, nullptr, nullptr, 0.0f, 0, st));
+    HIPCHK("sqs ones", launch_update(p, UPD_ONES, nullptr, nullptr, nullptr, nullptr, 0.0f, 0, nullptr, st));
     for (int m = 0; m < p->M; ++m) {
         HIPCHK("sqs project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), nullptr,
                                         w_full + subset_ray0(p, m), p->d_r, 0, 0, nullptr, 0, st));
@@ -157,7 +157,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
 
     if (s->step == 0) {
         HIPCHK("iterate scalars", launch_set_scalars(p, 0, opt->continuation ? 1.0 : opt->rho_fixed, 0, st));
-        HIPCHK("iterate layout", launch_update(p, UPD_LAYOUT, s->x, nullptr, nullptr, nullptr, 0.0f, 0, st));
+        HIPCHK("iterate layout", launch_update(p, UPD_LAYOUT, s->x, nullptr, nullptr, nullptr, 0.0f, 0, nullptr, st));
         const int m0 = p->order[0];
         HIPCHK("iterate init project", launch_fp(p, subset_slot0(p, m0), subset_nview(p, m0),
                                                  prob->y + subset_ray0(p, m0), prob->w + subset_ray0(p, m0),
@@ -169,13 +169,19 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
         HIPCHK("iterate scalars", launch_set_scalars(p, s->l, rho, s->step, st));
         HIPCHK("iterate resume", launch_reg_grad(p, s->x, beta, inv_delta2, st));
     }
+    // The continuation decision after a step's back-projection is taken by
+    // a one-block kernel, or in 2D by the next step's x-update kernel
+    // (fused: every block reduces the epilogue's partials; 3D has too many
+    // partials for that).  No decision stays pending between calls.
+    bool pending = false;
     for (int64_t t = 0; t < n_steps; ++t) {
         const int64_t j = s->step + t;
         const int m = p->order[(size_t)((j + 1) % M)];
         {
             ProfScope ps(p, 0, st);
             HIPCHK("iterate update", launch_update(p, UPD_STEP, s->x, s->grad, s->g, prob->denom, beta,
-                                                   prob->nonneg, st));
+                                                   prob->nonneg, pending ? &e.cont : nullptr, st));
+            pending = false;
         }
         {
             ProfScope ps(p, 1, st);
@@ -187,9 +193,12 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
             ProfScope ps(p, 2, st);
             HIPCHK("iterate backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r,
                                                     BP_STEP, e, st));
+            if (p->is3d) HIPCHK("iterate finalize", launch_finalize(p, e.cont, st));
+            else pending = true;
         }
     }
-    HIPCHK("iterate readback", hipMemcpyAsync(p->h_sc, p->d_sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    if (pending) HIPCHK("iterate finalize", launch_finalize(p, e.cont, st));
+    HIPCHK("iterate readback", hipMemcpyAsync(p->h_sc, cur_sc(p), sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK("iterate sync", hipStreamSynchronize(st));
     prof_collect(p);
     s->step = p->h_sc->step;
@@ -207,7 +216,7 @@ extern "C" lalm_status lalm_cost_f64(lalm_plan *p, const lalm_problem *prob, con
         return fail(LALM_E_INVALID, "lalm_cost_f64: null argument");
     if (!(prob->delta > 0.0)) return fail(LALM_E_INVALID, "lalm_cost_f64: need delta > 0");
     HIPCHK("cost layout", launch_update(p, UPD_LAYOUT, const_cast<float *>(x), nullptr, nullptr, nullptr,
-                                        0.0f, 0, st));
+                                        0.0f, 0, nullptr, st));
     for (int m = 0; m < p->M; ++m) {
         int64_t nblk = 0;
         HIPCHK("cost project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), prob->y + subset_ray0(p, m),

@@ -90,46 +90,6 @@ __device__ inline double block_sum_256(double v, double *lds)
     return t;   // valid in thread 0
 }
 
-// Last block of a back-projection: continuation update of Sec. III-B from
-// the FP64 total of the restart indicator (STEP) or the finite check (INIT).
-template <int MODE>
-__device__ void finalize_continuation(const BPArgs &A, double total)
-{
-    DevScalars *sc = A.sc;
-    const ContArgs &C = A.e.cont;
-    if (MODE == BP_INIT) {
-        if (!isfinite(total)) sc->status = 1;
-    } else {
-        const long long jstep = sc->step;
-        const double rho_used = sc->rho;
-        bool restart = false;
-        if (!isfinite(total)) {
-            sc->status = 1;
-        } else if (C.continuation) {
-            restart = total > 0.0;
-            if (C.forced && jstep < C.forced_len) restart = C.forced[jstep] != 0;
-            const long long l = restart ? 0 : sc->l + 1;
-            sc->l = l;
-            double nr;
-            if (l == 0) {
-                nr = 1.0;
-            } else {
-                const double pi = 3.14159265358979323846;
-                const double a = pi / (2.0 * (double)(l + 1));
-                nr = fmax(pi / (double)(l + 1) * sqrt(1.0 - a * a), C.rho_min);
-            }
-            sc->rho = nr;
-        }
-        sc->xi = total;
-        if (jstep < C.st_cap) {
-            if (C.st_rho) C.st_rho[jstep] = rho_used;
-            if (C.st_xi) C.st_xi[jstep] = total;
-            if (C.st_restart) C.st_restart[jstep] = restart ? 1 : 0;
-        }
-        sc->step = jstep + 1;
-    }
-}
-
 template <bool IS3D, int MODE>
 __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 {
@@ -275,7 +235,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 // kernel adds the two partial images and applies the OS-LALM update.
 constexpr int BP2_VG = 8;      // waves (view groups) per block
 constexpr int BP2_TR = 16;     // band width of a tile
-constexpr int BP2_LD = 66;     // LDS stride between accumulator rows (bank spread)
+constexpr int BP2_LD = 64;     // LDS stride between accumulator rows: a row is one bank each per lane
 constexpr int BP2_ROWS = BP2_TR + 4;   // two padding rows on each side of the band
 constexpr int BP2_WMAX = 256;  // staged rays per wave and view
 
@@ -477,37 +437,30 @@ __global__ void __launch_bounds__(256) bp2d_epilogue_kernel(BPArgs A)
 }
 
 // One block: fixed-order FP64 sum of the back-projection's block partials,
-// then the continuation update (STEP) or the finite check (INIT).
+// then the continuation decision (STEP) or the finite check (INIT); reads
+// the scalar record `in`, writes the next one to `out`.
 template <int MODE>
-__global__ void __launch_bounds__(256) finalize_kernel(BPArgs A)
+__global__ void __launch_bounds__(256) finalize_kernel(const double *partials, long long nblocks,
+                                                       const DevScalars *in, DevScalars *out, ContArgs C)
 {
-    if (A.sc->status) return;
-    __shared__ double s_tree[256];
+    __shared__ double s_w[4];
     const int tid = threadIdx.x;
-    double v = 0.0;
-    for (int t = tid; t < A.nblocks; t += 256) v += A.partials[t];
-    s_tree[tid] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) s_tree[tid] += s_tree[tid + w];
-        __syncthreads();
+    const DevScalars s = *in;
+    if (s.status) {
+        if (tid == 0) *out = s;
+        return;
     }
-    if (tid == 0) finalize_continuation<MODE>(A, s_tree[0]);
+    const double total = fixed_sum_256(partials, nblocks, tid, s_w);
+    if (tid == 0) *out = continuation_update(s, C, total, MODE == BP_INIT, true);
 }
 
 template <bool IS3D>
 hipError_t bp_dispatch(const BPArgs &a, int mode, dim3 grd, hipStream_t st)
 {
     dim3 blk(32, 8);
-    if (mode == BP_PLAIN) {
-        hipLaunchKernelGGL((bp_kernel<IS3D, BP_PLAIN>), grd, blk, 0, st, a);
-    } else if (mode == BP_INIT) {
-        hipLaunchKernelGGL((bp_kernel<IS3D, BP_INIT>), grd, blk, 0, st, a);
-        hipLaunchKernelGGL((finalize_kernel<BP_INIT>), dim3(1), dim3(256), 0, st, a);
-    } else {
-        hipLaunchKernelGGL((bp_kernel<IS3D, BP_STEP>), grd, blk, 0, st, a);
-        hipLaunchKernelGGL((finalize_kernel<BP_STEP>), dim3(1), dim3(256), 0, st, a);
-    }
+    if (mode == BP_PLAIN) hipLaunchKernelGGL((bp_kernel<IS3D, BP_PLAIN>), grd, blk, 0, st, a);
+    else if (mode == BP_INIT) hipLaunchKernelGGL((bp_kernel<IS3D, BP_INIT>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((bp_kernel<IS3D, BP_STEP>), grd, blk, 0, st, a);
     return hipGetLastError();
 }
 
@@ -537,7 +490,7 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.e = e;
     if (mode != BP_PLAIN) a.e.out = p->d_gradR;
     a.partials = p->d_partials;
-    a.sc = p->d_sc;
+    a.sc = cur_sc(p);
     a.part = p->d_part;
     a.part2 = p->d_part2;
     a.check_status = mode != BP_PLAIN;
@@ -547,21 +500,33 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
         hipLaunchKernelGGL(bp2d_lines_kernel, dim3(nxt + nyt), dim3(64, BP2_VG), 0, st, a, nxt);
         dim3 ge((p->nx + 31) / 32, (p->ny + 7) / 8);
         a.nblocks = (int)(ge.x * ge.y);
-        if (mode == BP_PLAIN) {
-            hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_PLAIN>), ge, dim3(32, 8), 0, st, a);
-        } else if (mode == BP_INIT) {
-            hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_INIT>), ge, dim3(32, 8), 0, st, a);
-            hipLaunchKernelGGL((finalize_kernel<BP_INIT>), dim3(1), dim3(256), 0, st, a);
-        } else {
-            hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_STEP>), ge, dim3(32, 8), 0, st, a);
-            hipLaunchKernelGGL((finalize_kernel<BP_STEP>), dim3(1), dim3(256), 0, st, a);
-        }
-        return hipGetLastError();
+        if (mode == BP_PLAIN) hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_PLAIN>), ge, dim3(32, 8), 0, st, a);
+        else if (mode == BP_INIT) hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_INIT>), ge, dim3(32, 8), 0, st, a);
+        else hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_STEP>), ge, dim3(32, 8), 0, st, a);
+    } else {
+        const int kz = KZ3;
+        dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + kz - 1) / kz);
+        a.nblocks = (int)(grd.x * grd.y * grd.z);
+        hipError_t e = bp_dispatch<true>(a, mode, grd, st);
+        if (e != hipSuccess) return e;
     }
-    const int kz = KZ3;
-    dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + kz - 1) / kz);
-    a.nblocks = (int)(grd.x * grd.y * grd.z);
-    return bp_dispatch<true>(a, mode, grd, st);
+    if (mode == BP_PLAIN) return hipGetLastError();
+    p->bp_nblocks = a.nblocks;
+    if (mode == BP_INIT) {
+        // finite check of the initial gradient: scalars advance to the other record
+        hipLaunchKernelGGL((finalize_kernel<BP_INIT>), dim3(1), dim3(256), 0, st, (const double *)p->d_partials,
+                           p->bp_nblocks, (const DevScalars *)cur_sc(p), p->d_sc + (p->sc_cur ^ 1), e.cont);
+        p->sc_cur ^= 1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st)
+{
+    hipLaunchKernelGGL((finalize_kernel<BP_STEP>), dim3(1), dim3(256), 0, st, (const double *)p->d_partials,
+                       p->bp_nblocks, (const DevScalars *)cur_sc(p), p->d_sc + (p->sc_cur ^ 1), c);
+    p->sc_cur ^= 1;
+    return hipGetLastError();
 }
 
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,

@@ -72,7 +72,7 @@ struct GeoK {
     long long slabT, slabN;   // elements per slice of the dominant axis
 };
 
-// Continuation bookkeeping handed to the back-projection epilogue.
+// Continuation bookkeeping (restart rule, rho schedule, statistics).
 struct ContArgs {
     int continuation;
     double rho_fixed, rho_min;
@@ -82,6 +82,67 @@ struct ContArgs {
     uint8_t *st_restart;
     long long st_cap;
 };
+
+// Fixed-order FP64 sum of v[0..n): thread t < 256 adds v[t], v[t+256], ...
+// in turn, each of the four waves combines its lanes by an xor butterfly,
+// then (w0 + w1) + (w2 + w3).  Every block that calls it gets the same bits.
+// All threads of the block must call it (tid = linear thread index, blocks
+// of >= 256 threads, wave64); s_w holds 4 doubles of LDS.
+__device__ inline double fixed_sum_256(const double *v, long long n, int tid, double *s_w)
+{
+    double a = 0.0;
+    if (tid < 256)
+        for (long long t = tid; t < n; t += 256) a += v[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (tid < 256 && (tid & 63) == 0) s_w[tid >> 6] = a;
+    __syncthreads();
+    const double r = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+    __syncthreads();
+    return r;
+}
+
+// rho_l of the downward continuation (eq. rho_l_formula_qp): 1 at l = 0,
+// else (pi/(l+1)) sqrt(1 - (pi/(2(l+1)))^2), never below rho_min.
+__device__ inline double continuation_rho(long long l, double rho_min)
+{
+    if (l == 0) return 1.0;
+    const double pi = 3.14159265358979323846;
+    const double a = pi / (2.0 * (double)(l + 1));
+    return fmax(pi / (double)(l + 1) * sqrt(1.0 - a * a), rho_min);
+}
+
+// Decision after the back-projection of step in.step, from its restart
+// indicator xi (Sec. III-B: restart, i.e. l = 0, when xi > 0): returns the
+// scalars of the next step.  init: after the initial gradient, only the
+// finite check.  record: write the step's statistics (one thread only).
+__device__ inline DevScalars continuation_update(const DevScalars &in, const ContArgs &C, double xi, bool init,
+                                                 bool record)
+{
+    DevScalars o = in;
+    if (init) {
+        if (!isfinite(xi)) o.status = 1;
+        return o;
+    }
+    const long long jstep = in.step;
+    bool restart = false;
+    if (!isfinite(xi)) {
+        o.status = 1;
+    } else if (C.continuation) {
+        restart = xi > 0.0;
+        if (C.forced && jstep < C.forced_len) restart = C.forced[jstep] != 0;
+        o.l = restart ? 0 : in.l + 1;
+        o.rho = continuation_rho(o.l, C.rho_min);
+    }
+    o.xi = xi;
+    if (record && jstep < C.st_cap) {
+        if (C.st_rho) C.st_rho[jstep] = in.rho;
+        if (C.st_xi) C.st_xi[jstep] = xi;
+        if (C.st_restart) C.st_restart[jstep] = restart ? 1 : 0;
+    }
+    o.step = jstep + 1;
+    return o;
+}
 
 }  // namespace lalm
 
@@ -112,7 +173,13 @@ struct lalm_plan {
     float *d_part2 = nullptr;           // 2D: back-projection of the y-dominant rays
     double *d_partials = nullptr;       // reduction partials
     int64_t n_partials = 0;
-    lalm::DevScalars *d_sc = nullptr;
+    // two device scalar records: each continuation decision reads one and
+    // writes the other (kernels of a launch that make the decision
+    // redundantly per block never see a half-updated record); sc_cur is the
+    // host's index of the current one, advanced in launch order
+    lalm::DevScalars *d_sc = nullptr;   // [2]
+    mutable int sc_cur = 0;
+    mutable long long bp_nblocks = 0;   // partials written by the last STEP back-projection
     lalm::DevScalars *h_sc = nullptr;   // pinned host mirror
     double *d_tmp = nullptr;            // small FP64 scratch (monitors)
     int fp_nseg = 1;
@@ -137,6 +204,8 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
                      const float *w, float *out, int mode, int64_t part_off,
                      int64_t *n_blocks_out, int check_status, hipStream_t st);
 
+inline lalm::DevScalars *cur_sc(const lalm_plan *p) { return p->d_sc + p->sc_cur; }
+
 enum BpMode { BP_PLAIN = 0, BP_INIT = 1, BP_STEP = 2 };
 struct BpEpi {
     float scale;           // PLAIN: scale; INIT/STEP: M
@@ -147,12 +216,20 @@ struct BpEpi {
     float beta, inv_delta2;   // regularizer: beta, 1/delta^2
     ContArgs cont;
 };
+// BP_INIT includes its finite check (the scalars advance); BP_STEP leaves
+// the continuation decision of the step to the next x-update or to
+// launch_finalize.
 hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *r, int mode,
                      const BpEpi &e, hipStream_t st);
+// Standalone continuation decision after the last BP_STEP of a call.
+hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st);
 
 enum UpdMode { UPD_LAYOUT = 0, UPD_ONES = 1, UPD_STEP = 2 };
+// UPD_STEP with cont != null first makes the pending continuation decision
+// of the previous step (fused, every block computes it; one records it).
 hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
-                         const float *denom, float beta, int nonneg, hipStream_t st);
+                         const float *denom, float beta, int nonneg, const ContArgs *cont,
+                         hipStream_t st);
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,
                            hipStream_t st);
 hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,

@@ -290,7 +290,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(dev_alloc(&p->d_part, nvox));
     chk(dev_alloc(&p->d_part2, nvox));
     chk(dev_alloc(&p->d_partials, (size_t)p->n_partials));
-    chk(dev_alloc(&p->d_sc, 1));
+    chk(dev_alloc(&p->d_sc, 2));
     chk(dev_alloc(&p->d_tmp, (size_t)(64 + M)));
     if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_sc, sizeof(lalm::DevScalars), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -306,7 +306,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(hipMemset(p->d_xt, 0, (size_t)g.nx * K.slabT * sizeof(float)));
     chk(hipMemset(p->d_xn, 0, (size_t)g.ny * K.slabN * sizeof(float)));
     chk(hipMemset(p->d_gradR, 0, nvox * sizeof(float)));
-    chk(hipMemset(p->d_sc, 0, sizeof(lalm::DevScalars)));
+    chk(hipMemset(p->d_sc, 0, 2 * sizeof(lalm::DevScalars)));
     chk(hipDeviceSynchronize());
     if (e != hipSuccess) {
         lalm::set_error(std::string("plan upload failed: ") + hipGetErrorString(e));

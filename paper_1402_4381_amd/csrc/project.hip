@@ -197,9 +197,15 @@ struct UpdArgs {
     float *x;
     const float *G, *g, *gradR, *denom;
     float *XT, *XN;
-    const DevScalars *sc;
+    const DevScalars *sc;   // scalars of this step (or of the previous one, do_finalize)
     float beta;
     int nonneg;
+    // fused continuation decision of the previous step (UPD_STEP)
+    int do_finalize;
+    const double *partials;
+    long long nblocks;
+    DevScalars *sc_out;
+    ContArgs cont;
 };
 
 // Number-weighted neighbour sum 2 * sum_{k in N(j)} kappa_jk for voxel (i,j,k)
@@ -221,43 +227,64 @@ template <bool IS3D, int MODE>
 __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
 {
     const GeoK &K = A.k;
-    if (MODE == UPD_STEP && A.sc->status) return;
     __shared__ float tile[32][33];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int k = blockIdx.z;
-    float rho = 1.0f;
-    if (MODE == UPD_STEP) rho = (float)A.sc->rho;
-    {
-        const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
-        float v = 0.0f;
-        if (i < K.nx && j < K.ny) {
-            const long long idx = ((long long)k * K.ny + j) * K.nx + i;
-            if (MODE == UPD_ONES) {
-                v = 1.0f;
-            } else {
-                v = A.x[idx];
-                if (MODE == UPD_STEP) {
-                    const float num = fmaf(rho, A.G[idx], (1.0f - rho) * A.g[idx]) + A.gradR[idx];
-                    const float den = fmaf(rho, A.denom[idx], A.beta * reg_curv_sum(K, i, j, k));
-                    if (den > 0.0f) {
-                        v = v - num / den;
-                        if (A.nonneg) v = fmaxf(v, 0.0f);
-                    }
-                    A.x[idx] = v;
-                }
+    const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
+    const bool inside = i < K.nx && j < K.ny;
+    const long long idx = ((long long)k * K.ny + j) * K.nx + i;
+    // operands first: their loads overlap the continuation decision below
+    float v = 0.0f, Gv = 0.0f, gv = 0.0f, rv = 0.0f, dv = 0.0f;
+    if (inside) {
+        if (MODE == UPD_ONES) {
+            v = 1.0f;
+        } else {
+            v = A.x[idx];
+            if (MODE == UPD_STEP) {
+                Gv = A.G[idx];
+                gv = A.g[idx];
+                rv = A.gradR[idx];
+                dv = A.denom[idx];
             }
-            const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
-                                         : ((long long)j * K.ldN + i + 2);
-            A.XN[n_idx] = v;
         }
-        tile[ty][tx] = v;
     }
+    if (MODE == UPD_STEP) {
+        __shared__ double s_w[4];
+        DevScalars s = *A.sc;
+        if (A.do_finalize) {
+            // every block takes the same decision from the same fixed-order
+            // sum; the first block records it in the other scalar record
+            const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tx == 0 && ty == 0;
+            if (!s.status) {
+                const double xi = fixed_sum_256(A.partials, A.nblocks, tx + 32 * ty, s_w);
+                s = continuation_update(s, A.cont, xi, false, lead);
+            }
+            if (lead) *A.sc_out = s;
+        }
+        if (s.status) return;
+        const float rho = (float)s.rho;
+        if (inside) {
+            const float num = fmaf(rho, Gv, (1.0f - rho) * gv) + rv;
+            const float den = fmaf(rho, dv, A.beta * reg_curv_sum(K, i, j, k));
+            if (den > 0.0f) {
+                v = v - num / den;
+                if (A.nonneg) v = fmaxf(v, 0.0f);
+            }
+            A.x[idx] = v;
+        }
+    }
+    if (inside) {
+        const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
+                                     : ((long long)j * K.ldN + i + 2);
+        A.XN[n_idx] = v;
+    }
+    tile[ty][tx] = v;
     __syncthreads();
     {
-        const int i = blockIdx.x * 32 + ty, j = blockIdx.y * 32 + tx;
-        if (i < K.nx && j < K.ny) {
-            const long long t_idx = IS3D ? ((long long)i * K.slabT + (long long)(k + 2) * K.ldT + j + 2)
-                                         : ((long long)i * K.ldT + j + 2);
+        const int it = blockIdx.x * 32 + ty, jt = blockIdx.y * 32 + tx;
+        if (it < K.nx && jt < K.ny) {
+            const long long t_idx = IS3D ? ((long long)it * K.slabT + (long long)(k + 2) * K.ldT + jt + 2)
+                                         : ((long long)it * K.ldT + jt + 2);
             A.XT[t_idx] = tile[tx][ty];
         }
     }
@@ -305,7 +332,7 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.w = w;
     a.out = out;
     a.partials = p->d_partials + part_off;
-    a.status = check_status ? &p->d_sc->status : nullptr;
+    a.status = check_status ? &cur_sc(p)->status : nullptr;
     long long nblk = (a.nrays + 63) / 64;
     if (n_blocks_out) *n_blocks_out = nblk;
     if (nblk == 0) return hipSuccess;
@@ -314,7 +341,7 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
 }
 
 hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
-                         const float *denom, float beta, int nonneg, hipStream_t st)
+                         const float *denom, float beta, int nonneg, const ContArgs *cont, hipStream_t st)
 {
     UpdArgs a;
     a.k = p->k;
@@ -325,16 +352,24 @@ hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G,
     a.denom = denom;
     a.XT = p->d_xt;
     a.XN = p->d_xn;
-    a.sc = p->d_sc;
+    a.sc = cur_sc(p);
     a.beta = beta;
     a.nonneg = nonneg;
-    return p->is3d ? upd_dispatch<true>(a, mode, st) : upd_dispatch<false>(a, mode, st);
+    a.do_finalize = (mode == UPD_STEP && cont) ? 1 : 0;
+    a.partials = p->d_partials;
+    a.nblocks = p->bp_nblocks;
+    a.sc_out = p->d_sc + (p->sc_cur ^ 1);
+    if (a.do_finalize) a.cont = *cont;
+    else a.cont = ContArgs{};
+    hipError_t e = p->is3d ? upd_dispatch<true>(a, mode, st) : upd_dispatch<false>(a, mode, st);
+    if (a.do_finalize) p->sc_cur ^= 1;
+    return e;
 }
 
 hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, p->d_sc, l, rho, step);
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, cur_sc(p), l, rho, step);
     return hipGetLastError();
 }
 
