@@ -276,17 +276,21 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Two taps of one sample into the lane's accumulator column.  jj is the lower
-// tap's row relative to the band; rows outside the band land in the padding.
 // Accumulator slot of (row, lane) in a wave's slab.
 __device__ inline int acc_slot(int row, int lane) { return row * BP2_LD + lane; }
 
-__device__ inline void splat2(float *slab, int lane, int jj, float f, float val)
+// Two taps of one sample into the lane's accumulator column: rows fl and
+// fl + 1 of the image, i.e. slab rows fl - band_base + 2 and + 3.  fl is
+// clamped into [band_base - 2, band_base + TR] (rows outside the band land in
+// the padding); lane_off = lane + (2 - band_base) * LD.
+__device__ inline void splat2(float *slab, int lane_off, float fl, float flo, float fhi, float f, float val)
 {
-    jj = min(max(jj, -2), BP2_TR);
-    slab[acc_slot(jj + 2, lane)] += (1.0f - f) * val;
-    slab[acc_slot(jj + 3, lane)] += f * val;
+    const int row = (int)__builtin_amdgcn_fmed3f(fl, flo, fhi);
+    float *p = slab + (row * BP2_LD + lane_off);
+    p[0] += (1.0f - f) * val;
+    p[BP2_LD] += f * val;
 }
+
 __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int nxt)
 {
     const GeoK &K = A.k;
@@ -315,6 +319,8 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
                            : fmaf((float)(band_base + BP2_TR), K.dy, K.y0);
     const float sf = (float)own;
     const int last = min(63, n_own - 1 - own_base);   // last active lane
+    const int lane_off = lane + (2 - band_base) * BP2_LD;
+    const float flo = (float)(band_base - 2), fhi = (float)(band_base + BP2_TR);
 
     for (int kv = wv; kv < A.nview; kv += BP2_VG) {
         const ViewRec V = A.views[kv];
@@ -361,21 +367,21 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
                 for (int u = 0; u < 4; ++u) {
                     const float eta = fmaf(sf, q[u].y, q[u].x);
                     const float fl = floorf(eta);
-                    splat2(slab, lane, (int)fl - band_base, eta - fl, q[u].z);
+                    splat2(slab, lane_off, fl, flo, fhi, eta - fl, q[u].z);
                 }
             }
             for (; b <= b1; ++b) {
                 const float4 q0 = st[b - wlo];
                 const float eta0 = fmaf(sf, q0.y, q0.x);
                 const float fl0 = floorf(eta0);
-                splat2(slab, lane, (int)fl0 - band_base, eta0 - fl0, q0.z);
+                splat2(slab, lane_off, fl0, flo, fhi, eta0 - fl0, q0.z);
             }
         } else {
             for (int b = b0; b <= b1; ++b) {           // wide window: read rays directly
                 const RayRec q = R[b];
                 const float eta = fmaf(sf, q.c, q.a);
                 const float fl = floorf(eta);
-                splat2(slab, lane, (int)fl - band_base, eta - fl, q.sc * rv[b]);
+                splat2(slab, lane_off, fl, flo, fhi, eta - fl, q.sc * rv[b]);
             }
         }
     }
