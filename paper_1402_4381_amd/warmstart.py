@@ -363,6 +363,118 @@ def _summary(rows, ws):
     return out
 
 
+def run_volume(name, weights, iters_in=2, iters_cmp=30, iters_ref=100, batch=8, dev="cuda:0"):
+    """Per-slice warm start on a 3D workload (the network trained on 2D
+    slices is applied to every axial slice of the 2-iteration volume), with
+    the FP64 cost guard of the whole volume and the state reset.  The
+    reference is the plain OS-LALM volume after iters_ref iterations (a
+    converged one-subset run is out of reach at this size); the warm path is
+    run to the same count and the two iters_ref volumes are compared as a
+    measure of the reference's own uncertainty."""
+    import torch
+    import synth
+    from paper_1402_4381_amd import lalm
+    cfg = synth.get_config(name)
+    M = cfg["M"]
+    nz, ny, nx = cfg["nz"], cfg["ny"], cfg["nx"]
+    t0 = time.perf_counter()
+    data = synth.make_problem_data(cfg)
+    t_data = time.perf_counter() - t0
+    print("volume %s: inputs in %.1f s" % (name, t_data), flush=True)
+    plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    vos = torch.as_tensor(plan.view_of_slot, dtype=torch.long, device=dev)
+    y = torch.as_tensor(data["y"].astype(np.float32), device=dev).index_select(0, vos).reshape(-1).contiguous()
+    w = torch.as_tensor(data["w"].astype(np.float32), device=dev).index_select(0, vos).reshape(-1).contiguous()
+    del data
+    denom = torch.empty(plan.image_elems, device=dev)
+    lalm.lalm_sqs_denom(plan, w, denom)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    radius, hu, in_scale = synth.roi_radius(cfg), synth.HU_PER_MU, 1.0 / synth.MU_WATER
+    r64 = torch.zeros(1, dtype=torch.float64, device=dev)
+    c64 = torch.zeros(3, dtype=torch.float64, device=dev)
+
+    def step(state, n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lalm.lalm_iterate(plan, y, w, denom, beta, delta, state, n * M)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def rmsd(a, b):
+        lalm.lalm_roi_rmsd_f64(plan, a, b, radius, r64)
+        return float(r64.item()) * hu
+
+    def cost(x):
+        lalm.lalm_cost_f64(plan, y, w, beta, delta, x, c64)
+        return float(c64[0].item())
+
+    zero = lambda: lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+    # plain OS-LALM to the reference count; iterates 1..iters_cmp kept
+    st = zero()
+    plain, t_plain = [], []
+    for k in range(iters_ref):
+        t_plain.append(step(st, 1))
+        if k < iters_cmp:
+            plain.append(st.x.clone())
+        if k + 1 == iters_ref - 10:
+            x_prev10 = st.x.clone()
+        if (k + 1) % 10 == 0:
+            print("  plain iteration %d  (%.3f s per iteration)" % (k + 1, t_plain[-1]), flush=True)
+    x_ref = st.x.clone()
+    ref_change = rmsd(x_ref, x_prev10)
+    plain_hu = [rmsd(x, x_ref) for x in plain]
+    del plain
+    # warm start: iters_in iterations, the network per slice, guard, reset
+    params = torch.as_tensor(np.load(weights), device=dev).contiguous()
+    net = lalm.lalm_unet_create(batch, ny, nx)
+    st2 = zero()
+    t_in = step(st2, iters_in)
+    x_in = st2.x.clone()
+    xt = torch.empty_like(x_in)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hw = ny * nx
+    for z0 in range(0, nz, batch):
+        b = min(batch, nz - z0)
+        lalm.lalm_unet_forward(net, params, x_in[z0 * hw:(z0 + b) * hw], xt[z0 * hw:(z0 + b) * hw], b,
+                               in_scale, True)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    psi_in, psi_net = cost(x_in), cost(xt)
+    t_guard = time.perf_counter() - t1
+    kept = psi_net < psi_in
+    print("  network on %d slices: %.3f s; guard %.3f s; Psi %.6e -> %.6e, kept %s"
+          % (nz, t_net, t_guard, psi_in, psi_net, kept), flush=True)
+    if kept:
+        st2 = lalm.LalmState(xt.clone(), torch.zeros_like(xt), torch.zeros_like(xt))
+    warm_hu, t_warm = [], []
+    for k in range(iters_ref - iters_in):
+        t_warm.append(step(st2, 1))
+        if k < iters_cmp - iters_in:
+            warm_hu.append(rmsd(st2.x, x_ref))
+        if (k + 1) % 10 == 0:
+            print("  warm iteration %d" % (iters_in + k + 1), flush=True)
+    final_diff = rmsd(st2.x, x_ref)
+    first = lambda v, thr: next((i for i, e in enumerate(v) if e < thr), None)
+    res = dict(workload=name, M=M, iters_in=iters_in, iters_ref=iters_ref, kept=kept,
+               inputs_s=round(t_data, 1), s_per_iteration=round(float(np.median(t_plain)), 4),
+               unet_s=round(t_net, 4), unet_slices=nz, guard_s=round(t_guard, 4),
+               psi_in=psi_in, psi_net=psi_net,
+               ref_last10_change_hu=round(ref_change, 4), warm_vs_plain_at_ref_hu=round(final_diff, 4),
+               rmsd_hu_in=round(rmsd(x_in, x_ref), 3), rmsd_hu_unet=round(rmsd(xt, x_ref), 3),
+               rmsd_hu_plain=[round(v, 3) for v in plain_hu],
+               rmsd_hu_warm=[round(v, 3) for v in warm_hu])
+    for thr in (10.0, 5.0, 2.0, 1.0):
+        kp, kw = first(plain_hu, thr), first(warm_hu, thr)
+        res["to_%g_hu" % thr] = dict(
+            plain_iters=None if kp is None else kp + 1,
+            warm_iters=None if kw is None else iters_in + kw + 1,
+            plain_s=None if kp is None else round(sum(t_plain[:kp + 1]), 3),
+            warm_s=None if kw is None else round(t_in + t_net + t_guard + sum(t_warm[:kw + 1]), 3))
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="U-Net warm start for OS-LALM: pairs, training, evaluation")
     ap.add_argument("--workload", default="fan2d_512")
@@ -376,11 +488,21 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=14)
     ap.add_argument("--weights", default=WEIGHTS, help="weights file to write (train) or read (eval only)")
     ap.add_argument("--eval-only", action="store_true")
+    ap.add_argument("--volume", default=None,
+                    help="3D workload: per-slice warm start with the committed weights (no training)")
     ap.add_argument("--out", default=None, help="JSON summary path")
     args = ap.parse_args(argv)
 
     import multiprocessing as mp
     import synth
+    if args.volume:
+        res = run_volume(args.volume, args.weights)
+        print(json.dumps({k: v for k, v in res.items() if not k.startswith("rmsd_hu_p")}), flush=True)
+        if args.out:
+            os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+            with open(args.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return res
     cfg = synth.get_config(args.workload)
     if cfg["kind"] != 0:
         raise SystemExit("the warm start is 2D (one network per slice image)")
