@@ -91,20 +91,51 @@ __device__ inline bf16x8 gather_ch(const bf16 *s1, const bf16 *s2, int c1, int c
     return ld8(s2 + pix * c2 + (c - c1));
 }
 
-// A tile (BM rows x BK) -> registers, one bf16x8 per slot
+// Per-slot state of an A-tile row that stays fixed over the K loop (A_CONV,
+// A_UPG): whether the row exists, its pixel coordinates and the index of
+// its pixel (A_UPG: of the pixel's top-left child on the 2x grid).
+struct ARow {
+    int ok, y, x, pix;
+};
+
 template <int AMODE, int BM>
-__device__ inline void load_a(const GemmArgs &g, int m0, int k0, int tid, bf16x8 *ra)
+__device__ inline void init_rows(const GemmArgs &g, int m0, int tid, ARow *rs)
 {
-    constexpr int NVT = BM * BK / 8;                // vectors in the tile
-    constexpr int NV = (NVT + 255) / 256;           // vectors per thread
+    constexpr int NVT = BM * BK / 8;
+    constexpr int NV = (NVT + 255) / 256;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int s = tid + v * 256;
-        if (NVT % 256 != 0 && s >= NVT) {
-            ra[v] = zero8();
-            continue;
+        const int m = m0 + s / (BK / 8);
+        ARow r{0, 0, 0, 0};
+        if ((NVT % 256 == 0 || s < NVT) && m < g.M) {
+            int b, y, x;
+            pix_decode(m, g.gH, g.gW, b, y, x);
+            r.ok = 1;
+            r.y = y;
+            r.x = x;
+            r.pix = AMODE == A_UPG ? ((b * 2 * g.gH + 2 * y) * (2 * g.gW) + 2 * x) : m;
         }
-        if (AMODE == A_MC) {
+        rs[v] = r;
+    }
+}
+
+// A tile (BM rows x BK) -> registers, one bf16x8 per slot.  A_CONV / A_UPG:
+// the K step's tap (or 2x2 phase) and channel range are uniform; a row's
+// gather is one bounds test and one address per vector.
+template <int AMODE, int BM>
+__device__ inline void load_a(const GemmArgs &g, const ARow *rs, int m0, int k0, int tid, bf16x8 *ra)
+{
+    constexpr int NVT = BM * BK / 8;                // vectors in the tile
+    constexpr int NV = (NVT + 255) / 256;           // vectors per thread
+    if (AMODE == A_MC) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int s = tid + v * 256;
+            if (NVT % 256 != 0 && s >= NVT) {
+                ra[v] = zero8();
+                continue;
+            }
             // slot -> (pixel kk, channel vector) ; channels along M
             const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
             const int k = k0 + kk, m = m0 + mv;
@@ -120,30 +151,44 @@ __device__ inline void load_a(const GemmArgs &g, int m0, int k0, int tid, bf16x8
                 }
             }
             ra[v] = r;
-        } else {
-            const int mm = s / (BK / 8), q = (s % (BK / 8)) * 8;
-            const int m = m0 + mm;
-            bf16x8 r = zero8();
-            if (m < g.M) {
-                int b, y, x;
-                pix_decode(m, g.gH, g.gW, b, y, x);
-                if (AMODE == A_CONV) {
-                    const int cin = g.ac1 + g.ac2;
-                    const int tap = k0 / cin, c = k0 - tap * cin + q;
-                    int yy = y, xx = x;
-                    if (g.ntap == 9) {
-                        yy += g.tsign * (tap / 3 - 1);
-                        xx += g.tsign * (tap % 3 - 1);
-                    }
-                    r = gather_ch(g.a1, g.a2, g.ac1, g.ac2, g.gH, g.gW, b, yy, xx, c);
-                } else {   // A_UPG: k = ab*Cs + c over the 2x grid
-                    const int ab = k0 / g.ac1, c = k0 - ab * g.ac1 + q;
-                    const long long pix = ((long long)b * 2 * g.gH + 2 * y + (ab >> 1)) * (2 * g.gW) + 2 * x + (ab & 1);
-                    r = ld8(g.a1 + pix * g.ac1 + c);
-                }
-            }
-            ra[v] = r;
         }
+        return;
+    }
+    // uniform over the block: source, channel offset and pixel shift of this K step
+    const bf16 *src;
+    int cs, c0, dy = 0, dx = 0, dpix;
+    if (AMODE == A_CONV) {
+        const int cin = g.ac1 + g.ac2;
+        const int tap = k0 / cin, c = k0 - tap * cin;
+        if (g.ntap == 9) {
+            dy = g.tsign * (tap / 3 - 1);
+            dx = g.tsign * (tap % 3 - 1);
+        }
+        const bool first = c < g.ac1;              // BK divides both channel counts
+        src = first ? g.a1 : g.a2;
+        cs = first ? g.ac1 : g.ac2;
+        c0 = first ? c : c - g.ac1;
+        dpix = dy * g.gW + dx;
+    } else {                                        // A_UPG: k = ab * C + c over the 2x grid
+        const int ab = k0 / g.ac1;
+        src = g.a1;
+        cs = g.ac1;
+        c0 = k0 - ab * g.ac1;
+        dpix = (ab >> 1) * 2 * g.gW + (ab & 1);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int s = tid + v * 256;
+        const int q = (s % (BK / 8)) * 8;
+        const ARow r = rs[v];
+        bool ok = r.ok != 0;
+        if (AMODE == A_CONV) {
+            const int yy = r.y + dy, xx = r.x + dx;
+            ok = ok && (unsigned)yy < (unsigned)g.gH && (unsigned)xx < (unsigned)g.gW;
+        }
+        const long long off = ok ? (long long)(r.pix + dpix) * cs + c0 + q : 0;
+        const bf16x8 val = ld8(src + off);
+        ra[v] = ok ? val : zero8();
     }
 }
 
@@ -239,13 +284,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     constexpr int NVA = (BM * BK / 8 + 255) / 256;
     constexpr int NVB = (BN * BK / 8 + 255) / 256;
     bf16x8 ra[NVA], rb[NVB];
+    ARow rs[NVA];
+    if (AMODE != A_MC) init_rows<AMODE, BM>(g, m0, tid, rs);
     floatx16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
 
     int buf = 0;
     if (kbeg < kend) {
-        load_a<AMODE, BM>(g, m0, kbeg, tid, ra);
+        load_a<AMODE, BM>(g, rs, m0, kbeg, tid, ra);
         load_b<BMODE, BN>(g, n0, kbeg, tid, rb);
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -253,7 +300,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         store_b<BMODE, BN>(Bs[buf], tid, rb);
         __syncthreads();
         if (k0 + BK < kend) {                      // prefetch the next tile
-            load_a<AMODE, BM>(g, m0, k0 + BK, tid, ra);
+            load_a<AMODE, BM>(g, rs, m0, k0 + BK, tid, ra);
             load_b<BMODE, BN>(g, n0, k0 + BK, tid, rb);
         }
         const bf16 *as = As[buf] + (wm * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
@@ -314,6 +361,116 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     }
 }
 
+// ------------------------------------------------------------------------
+// 3x3 convolution (forward, or the input gradient with mirrored taps) as an
+// implicit GEMM whose input tile is staged once per chunk of 32 channels.
+// A block owns a TH x 16 pixel tile of one image and BN output channels.  For
+// each chunk it loads the (TH + 2) x 18 pixel patch (zero outside the image)
+// and the BN x 9 x 32 weights into LDS; every wave then runs 9 taps x 2 MFMA
+// k-steps reading its operands from LDS, so the nine taps re-read the patch
+// in LDS instead of memory.  Same MFMA, operand layouts and epilogues as
+// gemm_kernel (E_FWD: bias, ReLU, bf16 NHWC; E_DG: FP32 split output).
+constexpr int CV_TW = 16;              // tile width (pixels)
+constexpr int CV_LDP = 40;             // LDS stride per patch pixel / weight tap (bf16): 32 + 8
+constexpr int CV_LDW = 9 * CV_LDP;     // LDS stride per weight row (9 taps)
+
+template <int EPI, int BM, int BN>
+__global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g)
+{
+    static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32x32");
+    static_assert(BM * (BN + 8) <= BN * CV_LDW, "epilogue staging fits in the weight buffer");
+    constexpr int TH = BM / CV_TW;                 // tile rows
+    constexpr int PH = TH + 2, PW = CV_TW + 2;     // patch with a one-pixel halo
+    __shared__ __attribute__((aligned(16))) bf16 Ps[PH * PW * CV_LDP];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[BN * CV_LDW];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv % (BM / 32), wn = wv / (BM / 32);
+    const int ntx = (g.gW + CV_TW - 1) / CV_TW, nty = (g.gH + TH - 1) / TH;
+    int t = blockIdx.x;
+    const int tx0 = (t % ntx) * CV_TW;
+    t /= ntx;
+    const int ty0 = (t % nty) * TH;
+    const int b = t / nty;
+    const int n0 = blockIdx.y * BN;
+    const int cin = g.ac1 + g.ac2;
+    floatx16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    // this lane's A row: tile pixel wm*32 + lane%32 (row-major TH x 16)
+    const int pr = wm * 32 + (lane & 31);
+    const int py = pr / CV_TW, px = pr % CV_TW;
+    for (int c0 = 0; c0 < cin; c0 += 32) {
+        const bool first = c0 < g.ac1;             // 32 divides both channel counts
+        const bf16 *src = first ? g.a1 : g.a2;
+        const int cs = first ? g.ac1 : g.ac2, cc = first ? c0 : c0 - g.ac1;
+        __syncthreads();                           // the previous chunk's readers are done
+        for (int s = tid; s < PH * PW * 4; s += 256) {
+            const int v = s & 3, pp = s >> 2;
+            const int yy = ty0 + pp / PW - 1, xx = tx0 + pp % PW - 1;
+            bf16x8 val = zero8();
+            if ((unsigned)yy < (unsigned)g.gH && (unsigned)xx < (unsigned)g.gW)
+                val = ld8(src + (((long long)b * g.gH + yy) * g.gW + xx) * cs + cc + 8 * v);
+            *reinterpret_cast<bf16x8 *>(Ps + pp * CV_LDP + 8 * v) = val;
+        }
+        for (int s = tid; s < BN * 36; s += 256) {  // [N][K] rows, K = tap * cin + c
+            const int v = s & 3, tp = (s >> 2) % 9, nn = s / 36;
+            bf16x8 val = zero8();
+            if (n0 + nn < g.N) val = ld8(g.w + (long long)(n0 + nn) * g.K + tp * cin + c0 + 8 * v);
+            *reinterpret_cast<bf16x8 *>(Ws + nn * CV_LDW + tp * CV_LDP + 8 * v) = val;
+        }
+        __syncthreads();
+        const bf16 *ws = Ws + (wn * 32 + (lane & 31)) * CV_LDW + 8 * (lane >> 5);
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) {
+            const int dy = g.tsign * (tp / 3 - 1), dx = g.tsign * (tp % 3 - 1);
+            const bf16 *ps = Ps + ((py + 1 + dy) * PW + px + 1 + dx) * CV_LDP + 8 * (lane >> 5);
+#pragma unroll
+            for (int kk = 0; kk < 32; kk += 16) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(ps + kk);
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(ws + tp * CV_LDP + kk);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc, 0, 0, 0);
+            }
+        }
+    }
+
+    // element t of acc: tile pixel wm*32 + 8(t/4) + 4(lane/32) + t%4, column wn*32 + lane%32
+    const int col = n0 + wn * 32 + (lane & 31);
+    if (EPI == E_FWD) {
+        __syncthreads();
+        bf16 *Cs = Ws;                             // BM x (BN + 8) bf16 staging
+        constexpr int LDC = BN + 8;
+        const float bv = (col < g.N && g.bias) ? g.bias[col] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            float v = acc[q] + bv;
+            if (g.relu) v = fmaxf(v, 0.0f);
+            Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
+        }
+        __syncthreads();
+        for (int s = tid; s < BM * (BN / 8); s += 256) {
+            const int r = s / (BN / 8), cv = (s % (BN / 8)) * 8;
+            const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW, n = n0 + cv;
+            if (y >= g.gH || x >= g.gW || n >= g.N) continue;
+            const long long pix = ((long long)b * g.gH + y) * g.gW + x;
+            *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
+        }
+    } else {
+        if (col >= g.N) return;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+            const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW;
+            if (y >= g.gH || x >= g.gW) continue;
+            const long long m = ((long long)b * g.gH + y) * g.gW + x;
+            if (col < g.oc1) g.o1[m * g.oc1 + col] = acc[q];
+            else g.o2[m * (g.N - g.oc1) + (col - g.oc1)] = acc[q];
+        }
+    }
+}
+
+
+
 template <int AMODE, int BMODE, int EPI>
 hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
 {
@@ -324,6 +481,20 @@ hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
         dim3 grd((g.M + 63) / 64, (g.N + 63) / 64, nsplit);
         hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 64, 64>), grd, dim3(256), 0, st, g);
     }
+    return hipGetLastError();
+}
+
+// 3x3 convolutions with 32 output channels take the patch-staged kernel
+// (its weights for 32 channels fit beside the patch); wider outputs keep
+// the generic implicit GEMM, whose smaller LDS footprint keeps more blocks
+// resident (measured faster for 64 and 128 channels).
+template <int EPI>
+hipError_t conv3x3(const GemmArgs &g, hipStream_t st)
+{
+    if (g.N > 32) return gemm<A_CONV, B_W, EPI>(g, 1, st);
+    const int ntx = (g.gW + CV_TW - 1) / CV_TW;
+    const dim3 grd(g.gB * ((g.gH + 7) / 8) * ntx, 1);
+    hipLaunchKernelGGL((conv3x3_kernel<EPI, 128, 32>), grd, dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
@@ -734,7 +905,7 @@ hipError_t conv_fwd(lalm_unet *n, int L, const bf16 *x1, int c1, const bf16 *x2,
     g.bias = params + n->boff[L];
     g.relu = 1;
     g.y = y;
-    return gemm<A_CONV, B_W, E_FWD>(g, 1, st);
+    return conv3x3<E_FWD>(g, st);
 }
 
 hipError_t up_fwd(lalm_unet *n, int L, const bf16 *x, bf16 *y, const float *params, int B, int h, int w,
@@ -851,7 +1022,7 @@ hipError_t conv_dgrad(lalm_unet *n, int L, const bf16 *dz, float *o1, int oc1, f
     g.ntap = 9; g.tsign = -1; g.ab = -1;
     g.w = n->wd[L];
     g.o1 = o1; g.o2 = o2; g.oc1 = oc1;
-    return gemm<A_CONV, B_W, E_DG>(g, 1, st);
+    return conv3x3<E_DG>(g, st);
 }
 
 // input gradient of a transposed conv: out[p][c] = sum_{ab, o} dz[up(p,ab)][o] W[ab][o][c]
