@@ -338,16 +338,47 @@ def _xstep(x, num, den, nonneg):
     return np.maximum(xn, 0.0) if nonneg else xn
 
 
+def inner_objective(z, x, s, DL, rho, beta, delta, is3d):
+    """Objective of the inner constrained-denoising problem of eq.
+    "os_lalm_iterates" with h = R + i_Omega (Sec. IV-A), up to a constant:
+    R(z) + rho/2 ||z - x||^2_{D_L} + <s, z - x>  (equal to
+    R(z) + rho/2 ||z - (x - (rho D_L)^-1 s)||^2_{D_L} where D_L > 0); the
+    constraint z >= 0 is not included."""
+    d = z - x
+    return float(reg_value(z, beta, delta, is3d) + 0.5 * rho * np.sum(DL * d * d) + np.sum(s * d))
+
+
+def inner_fista(x, s, DL, DR, rho, beta, delta, is3d, n, nonneg=True):
+    """n iterations of FISTA (Beck & Teboulle) on the inner problem of
+    :func:`inner_objective`, from the warm start z = x (Sec. IV-A).  The
+    smooth part's gradient rho D_L (z - x) + s + grad R(z) is majorized by the
+    diagonal rho D_L + D_R; the proximal step is the projection onto Omega
+    (the nonnegativity clamp).  Momentum: t_1 = 1,
+    t_{i+1} = (1 + sqrt(1 + 4 t_i^2)) / 2, z <- v_i + (t_i - 1)/t_{i+1} (v_i - v_{i-1}).
+    n = 1 is one projected gradient step from x."""
+    den = rho * DL + DR
+    v_prev, z, t = x, x, 1.0
+    for _ in range(n):
+        grad = rho * DL * (z - x) + s + reg_grad(z, beta, delta, is3d)
+        v = _xstep(z, grad, den, nonneg)
+        t_next = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        z = v + ((t - 1.0) / t_next) * (v - v_prev)
+        v_prev, t = v, t_next
+    return v_prev
+
+
 def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0,
             rho_min=1e-3, x0=None, denom=None, forced_restart=None, nonneg=True,
-            callback=None):
-    """OS-LALM with one inner step (n = 1), Sec. III-A eq. "os_lalm_iterates".
+            callback=None, n_inner=1):
+    """OS-LALM, Sec. III-A eq. "os_lalm_iterates".
 
     The substitution of eq. "ct_substitution" makes grad l_m the weighted
     subset gradient; the inner constrained-denoising problem
     min_z R(z) + i_Omega(z) + rho/2 ||z - (x - (rho D_L)^-1 s)||^2_{D_L}
-    gets one projected gradient step from the warm start z = x, with the
-    diagonal majorizer rho D_L + D_R (the first FISTA step has no momentum).
+    gets n_inner FISTA iterations from the warm start z = x
+    (:func:`inner_fista`); n_inner = 1 is one projected gradient step with
+    the diagonal majorizer rho D_L + D_R (the first FISTA step has no
+    momentum).
 
     Step j (0-based) visits subset order[(j + 1) mod M] for the gradient at
     the new image; the initial gradient is G = M grad l_{order[0]}(x0) and
@@ -375,8 +406,10 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     hist_rho, hist_xi, hist_rs = [], [], []
     for j in range(n_steps):
         s = rho * G + (1.0 - rho) * g
-        num = s + reg_grad(x, beta, delta, is3d)
-        x_new = _xstep(x, num, rho * DL + DR, nonneg)
+        if n_inner == 1:
+            x_new = _xstep(x, s + reg_grad(x, beta, delta, is3d), rho * DL + DR, nonneg)
+        else:
+            x_new = inner_fista(x, s, DL, DR, rho, beta, delta, is3d, n_inner, nonneg)
         G_new = subset_gradient(cfg, x_new, y, w, subsets[order[(j + 1) % M]], M)
         g_new = (rho * G_new + g) / (rho + 1.0)
         xi = float(np.sum((g - G_new) * (G_new - G)))

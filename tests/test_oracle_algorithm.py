@@ -258,3 +258,67 @@ def test_single_subset_continuation_reaches_fista_minimizer():
                       continuation=True, denom=DL)
     mask = synth.roi_mask(cfg)
     assert ora.rmsd_hu(out["x"], xs, mask, synth.HU_PER_MU) < 0.05
+
+
+# ---------------------------------------------------------------- inner FISTA (n > 1)
+
+def _inner_case(beta_scale=1.0, seed=7):
+    cfg = synth.get_config("tiny2d")
+    rng = np.random.default_rng(seed)
+    shape = ora.image_shape(cfg)
+    x = rng.uniform(0.0, 0.03, shape)
+    x[0, 0, :3] = 0.0                                  # some voxels on the constraint
+    DL = rng.uniform(0.5, 2.0, shape) * 1e3
+    s = rng.normal(0.0, 20.0, shape)
+    beta = beta_scale * 5.0
+    delta = synth.configs.delta_mu(cfg)
+    DR = ora.reg_denom(shape, beta, False)
+    return x, s, DL, DR, beta, delta
+
+
+def test_inner_fista_one_step_is_the_projected_gradient_step():
+    x, s, DL, DR, beta, delta = _inner_case()
+    rho = 0.3
+    v = ora.inner_fista(x, s, DL, DR, rho, beta, delta, False, 1)
+    ref = np.maximum(x - (s + ora.reg_grad(x, beta, delta, False)) / (rho * DL + DR), 0.0)
+    assert np.array_equal(v, ref)
+
+
+def test_inner_fista_without_regularizer_is_the_separable_closed_form():
+    """beta = 0: the inner problem separates, z* = max(0, x - s / (rho D_L)),
+    reached by the first step and kept by every later one."""
+    x, s, DL, DR, beta, delta = _inner_case(beta_scale=0.0)
+    rho = 0.2
+    closed = np.maximum(x - s / (rho * DL), 0.0)
+    for n in (1, 2, 5):
+        v = ora.inner_fista(x, s, DL, DR, rho, 0.0, delta, False, n)
+        np.testing.assert_allclose(v, closed, rtol=1e-12, atol=1e-15)
+
+
+def test_inner_fista_converges_to_the_bound_constrained_minimizer():
+    """Many FISTA iterations reach the minimizer found by an independent
+    bound-constrained quasi-Newton solver (scipy L-BFGS-B), and the inner
+    objective falls from n = 1 to n = 5."""
+    from scipy.optimize import minimize
+    x, s, DL, DR, beta, delta = _inner_case()
+    rho = 0.1
+    shape = x.shape
+    f = lambda z: ora.inner_objective(z.reshape(shape), x, s, DL, rho, beta, delta, False)
+    jac = lambda z: (rho * DL * (z.reshape(shape) - x) + s
+                     + ora.reg_grad(z.reshape(shape), beta, delta, False)).ravel()
+    res = minimize(f, x.ravel(), jac=jac, method="L-BFGS-B", bounds=[(0.0, None)] * x.size,
+                   options=dict(ftol=1e-15, gtol=1e-12, maxiter=10000))
+    v = ora.inner_fista(x, s, DL, DR, rho, beta, delta, False, 3000)
+    assert np.max(np.abs(v.ravel() - res.x)) <= 1e-6 * max(1e-3, np.max(np.abs(res.x)))
+    f1 = f(ora.inner_fista(x, s, DL, DR, rho, beta, delta, False, 1).ravel())
+    f5 = f(ora.inner_fista(x, s, DL, DR, rho, beta, delta, False, 5).ravel())
+    assert f5 < f1
+    assert f(v.ravel()) <= f5 + 1e-12 * abs(f5)
+
+
+def test_os_lalm_n_inner_one_matches_the_default():
+    cfg = synth.get_config("tiny2d")
+    d = synth.make_problem_data(cfg, workers=1)
+    a = ora.os_lalm(cfg, d["y"], d["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=3, n_steps=6)
+    b = ora.os_lalm(cfg, d["y"], d["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=3, n_steps=6, n_inner=1)
+    assert np.array_equal(a["x"], b["x"])
