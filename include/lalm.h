@@ -179,10 +179,15 @@ typedef struct {
 
 /* continuation: 1 = downward continuation with adaptive restart (Sec. III-B),
  * 0 = fixed rho = rho_fixed.  rho_min: lower bound of rho_l (1e-3 in the
- * paper).  n_inner: inner FISTA iterations for the constrained denoising
- * step; only 1 is implemented.  forced_restart: optional DEVICE array of
+ * paper).  n_inner: FISTA iterations (Beck & Teboulle) on the inner
+ * constrained-denoising problem of each step, from the warm start x (Sec.
+ * IV-A), 1 .. LALM_MAX_INNER; 1 is one projected, diagonally majorized
+ * gradient step (the paper's default), n > 1 costs n - 1 more image passes
+ * with a regularizer gradient each.  forced_restart: optional DEVICE array of
  * forced_len bytes indexed by global step; when step < forced_len its value
  * replaces the restart test (replay of a restart sequence). */
+#define LALM_MAX_INNER 16
+
 typedef struct {
     int32_t continuation;
     double rho_fixed, rho_min;
@@ -205,13 +210,14 @@ typedef struct {
  *   s = rho grad + (1 - rho) g,
  *   x <- max(0, x - (s + grad R(x)) / (rho denom + D_R))
  *        (one projected gradient step on the inner constrained denoising
- *        problem, n = 1; D_R = 2 beta sum kappa, the SQS curvature of R),
+ *        problem, n = 1; D_R = 2 beta sum kappa, the SQS curvature of R;
+ *        n_inner > 1 continues with FISTA iterations, see lalm_options),
  *   grad+ = M A_m' W_m (A_m x - y_m) with m = order[(j+1) mod M],
  *   g <- (rho grad+ + g) / (rho + 1),
  *   xi = <g_old - grad+, grad+ - grad_old> in FP64; with continuation,
  *   l <- 0 if xi > 0 else l + 1, and the next step uses rho_l.
  * Synchronizes the stream once at the end to return the continuation state.
- * Errors: LALM_E_INVALID for null pointers or n_inner != 1; LALM_E_STATE for
+ * Errors: LALM_E_INVALID for null pointers or n_inner outside [1, LALM_MAX_INNER]; LALM_E_STATE for
  * a negative step; LALM_E_NONFINITE when xi became non-finite (the state
  * then keeps the last image computed from finite gradients and later steps
  * are skipped).

@@ -123,7 +123,8 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     if (!p || !prob || !s || !opt) return fail(LALM_E_INVALID, "lalm_iterate: null argument");
     if (!prob->y || !prob->w || !prob->denom) return fail(LALM_E_INVALID, "lalm_iterate: null problem array");
     if (!s->x || !s->g || !s->grad) return fail(LALM_E_INVALID, "lalm_iterate: null state array");
-    if (opt->n_inner != 1) return fail(LALM_E_INVALID, "lalm_iterate: only n_inner = 1 is implemented");
+    if (opt->n_inner < 1 || opt->n_inner > LALM_MAX_INNER)
+        return fail(LALM_E_INVALID, "lalm_iterate: n_inner must lie in [1, LALM_MAX_INNER]");
     if (n_steps < 0) return fail(LALM_E_INVALID, "lalm_iterate: negative step count");
     if (!(prob->beta >= 0.0) || !(prob->delta > 0.0)) return fail(LALM_E_INVALID, "lalm_iterate: need beta >= 0, delta > 0");
     if (!(opt->rho_min > 0.0 && opt->rho_min <= 1.0)) return fail(LALM_E_INVALID, "lalm_iterate: rho_min must lie in (0, 1]");
@@ -179,9 +180,23 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
         const int m = p->order[(size_t)((j + 1) % M)];
         {
             ProfScope ps(p, 0, st);
+            const int n = opt->n_inner;
+            // FISTA on the inner problem: iteration 1 is the projected step
+            // from x (its momentum is zero); z ping-pongs between the two
+            // partial images, which the back-projector needs only later
+            float *zb[2] = {p->d_part, p->d_part2};
             HIPCHK("iterate update", launch_update(p, UPD_STEP, s->x, s->grad, s->g, prob->denom, beta,
-                                                   prob->nonneg, pending ? &e.cont : nullptr, st));
+                                                   prob->nonneg, pending ? &e.cont : nullptr, st,
+                                                   n > 1 ? p->d_v : nullptr, n > 1 ? zb[0] : nullptr));
             pending = false;
+            double tk = 0.5 * (1.0 + std::sqrt(5.0));     // t_2 (t_1 = 1)
+            for (int it = 2; it <= n; ++it) {
+                const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
+                const float mom = (float)((tk - 1.0) / tn);
+                HIPCHK("iterate inner", launch_inner(p, zb[it % 2], p->d_v, zb[(it + 1) % 2], s->x, s->grad, s->g,
+                                                     prob->denom, beta, inv_delta2, mom, prob->nonneg, it == n, st));
+                tk = tn;
+            }
         }
         {
             ProfScope ps(p, 1, st);

@@ -43,42 +43,6 @@ struct BPArgs {
     int check_status;  // 2D line kernel: skip when a non-finite indicator was met
 };
 
-// d psi / dt for the hyperbola potential: t / sqrt(1 + (t/delta)^2)
-__device__ inline float dpsi(float t, float inv_delta2)
-{
-    return t * rsqrtf(fmaf(t * t, inv_delta2, 1.0f));
-}
-
-// grad R at voxel (i, j, k): beta sum_{n in N} kappa psi'(x_c - x_n)
-template <bool IS3D>
-__device__ float reg_grad_at(const GeoK &K, const float *x, int i, int j, int k, float beta,
-                             float inv_delta2)
-{
-    const long long plane = (long long)K.nx * K.ny;
-    const long long c = (long long)k * plane + (long long)j * K.nx + i;
-    const float xc = x[c];
-    const float r2 = 0.70710678118654752f, r3 = 0.57735026918962576f;
-    float s = 0.0f;
-    const int zlo = IS3D ? -1 : 0, zhi = IS3D ? 1 : 0;
-#pragma unroll
-    for (int dz = zlo; dz <= zhi; ++dz) {
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dx == 0 && dy == 0 && dz == 0) continue;
-                const int ii = i + dx, jj = j + dy, kk = k + dz;
-                if (ii < 0 || ii >= K.nx || jj < 0 || jj >= K.ny || kk < 0 || kk >= K.nz) continue;
-                const int n = (dx != 0) + (dy != 0) + (dz != 0);
-                const float kap = n == 1 ? 1.0f : (n == 2 ? r2 : r3);
-                const float xn = x[c + (long long)dz * plane + (long long)dy * K.nx + dx];
-                s = fmaf(kap, dpsi(xc - xn, inv_delta2), s);
-            }
-        }
-    }
-    return beta * s;
-}
-
 __device__ inline double block_sum_256(double v, double *lds)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

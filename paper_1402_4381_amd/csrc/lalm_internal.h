@@ -102,6 +102,42 @@ __device__ inline double fixed_sum_256(const double *v, long long n, int tid, do
     return r;
 }
 
+// d psi / dt for the hyperbola potential: t / sqrt(1 + (t/delta)^2)
+__device__ inline float dpsi(float t, float inv_delta2)
+{
+    return t * rsqrtf(fmaf(t * t, inv_delta2, 1.0f));
+}
+
+// grad R at voxel (i, j, k): beta sum_{n in N} kappa psi'(x_c - x_n)
+template <bool IS3D>
+__device__ inline float reg_grad_at(const GeoK &K, const float *x, int i, int j, int k, float beta,
+                             float inv_delta2)
+{
+    const long long plane = (long long)K.nx * K.ny;
+    const long long c = (long long)k * plane + (long long)j * K.nx + i;
+    const float xc = x[c];
+    const float r2 = 0.70710678118654752f, r3 = 0.57735026918962576f;
+    float s = 0.0f;
+    const int zlo = IS3D ? -1 : 0, zhi = IS3D ? 1 : 0;
+#pragma unroll
+    for (int dz = zlo; dz <= zhi; ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                const int ii = i + dx, jj = j + dy, kk = k + dz;
+                if (ii < 0 || ii >= K.nx || jj < 0 || jj >= K.ny || kk < 0 || kk >= K.nz) continue;
+                const int n = (dx != 0) + (dy != 0) + (dz != 0);
+                const float kap = n == 1 ? 1.0f : (n == 2 ? r2 : r3);
+                const float xn = x[c + (long long)dz * plane + (long long)dy * K.nx + dx];
+                s = fmaf(kap, dpsi(xc - xn, inv_delta2), s);
+            }
+        }
+    }
+    return beta * s;
+}
+
 // rho_l of the downward continuation (eq. rho_l_formula_qp): 1 at l = 0,
 // else (pi/(l+1)) sqrt(1 - (pi/(2(l+1)))^2), never below rho_min.
 __device__ inline double continuation_rho(long long l, double rho_min)
@@ -171,6 +207,7 @@ struct lalm_plan {
     float *d_r = nullptr;               // subset residual
     float *d_part = nullptr;            // 2D: back-projection of the x-dominant rays
     float *d_part2 = nullptr;           // 2D: back-projection of the y-dominant rays
+    float *d_v = nullptr;               // inner FISTA iterate (n_inner > 1); part, part2 hold z
     double *d_partials = nullptr;       // reduction partials
     int64_t n_partials = 0;
     // two device scalar records: each continuation decision reads one and
@@ -227,9 +264,19 @@ hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st
 enum UpdMode { UPD_LAYOUT = 0, UPD_ONES = 1, UPD_STEP = 2 };
 // UPD_STEP with cont != null first makes the pending continuation decision
 // of the previous step (fused, every block computes it; one records it).
+// vout != null: first of several inner FISTA iterations -- the step's
+// result goes to vout and zout (the next momentum point) instead of x and
+// the projector layouts.
 hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
                          const float *denom, float beta, int nonneg, const ContArgs *cont,
-                         hipStream_t st);
+                         hipStream_t st, float *vout = nullptr, float *zout = nullptr);
+// Inner FISTA iteration i >= 2 on the constrained-denoising problem of the
+// current step: v = P(z - (rho D_L (z - x) + s + grad R(z)) / (rho D_L + D_R)),
+// s = rho G + (1 - rho) g; then zout = v + mom (v - v_prev) with v kept in
+// v (in place), or, last, x = v and the projector layouts.
+hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zout, float *x, const float *G,
+                        const float *g, const float *denom, float beta, float inv_delta2, float mom, int nonneg,
+                        bool last, hipStream_t st);
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,
                            hipStream_t st);
 hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,

@@ -206,6 +206,8 @@ struct UpdArgs {
     long long nblocks;
     DevScalars *sc_out;
     ContArgs cont;
+    // first of several inner iterations: v and the next momentum point go here
+    float *vout, *zout;
 };
 
 // Number-weighted neighbour sum 2 * sum_{k in N(j)} kappa_jk for voxel (i,j,k)
@@ -270,8 +272,14 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
                 v = v - num / den;
                 if (A.nonneg) v = fmaxf(v, 0.0f);
             }
-            A.x[idx] = v;
+            if (A.vout) {
+                A.vout[idx] = v;                  // first FISTA momentum is zero: z = v
+                A.zout[idx] = v;
+            } else {
+                A.x[idx] = v;
+            }
         }
+        if (A.vout) return;                       // the projector layouts follow the last inner iteration
     }
     if (inside) {
         const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
@@ -287,6 +295,70 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
                                          : ((long long)it * K.ldT + jt + 2);
             A.XT[t_idx] = tile[tx][ty];
         }
+    }
+}
+
+// ---------------------------------------------------------------- inner FISTA
+//
+// Iteration i >= 2 of the FISTA solve of the step's constrained-denoising
+// problem (Sec. IV-A), one thread per voxel of a 32x32 tile of one slice:
+// the gradient of the smooth part at the momentum point z is
+// rho D_L (z - x) + s + grad R(z), with s = rho G + (1 - rho) g; the step
+// uses the diagonal majorizer rho D_L + D_R and the nonnegativity
+// projection.  Not last: v (holding v_{i-1}) <- v_i, zout <- v_i + mom
+// (v_i - v_{i-1}).  Last: x <- v_i and the padded projector layouts.
+struct InnerArgs {
+    GeoK k;
+    const float *z, *G, *g, *denom;
+    float *v, *zout, *x, *XT, *XN;
+    const DevScalars *sc;
+    float beta, inv_delta2, mom;
+    int nonneg;
+};
+
+template <bool IS3D, bool LAST>
+__global__ void __launch_bounds__(1024) inner_kernel(InnerArgs A)
+{
+    const GeoK &K = A.k;
+    __shared__ float tile[32][33];
+    const DevScalars s = *A.sc;
+    if (s.status) return;
+    const float rho = (float)s.rho;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int k = blockIdx.z;
+    const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
+    const bool inside = i < K.nx && j < K.ny;
+    float v = 0.0f;
+    if (inside) {
+        const long long idx = ((long long)k * K.ny + j) * K.nx + i;
+        const float zv = A.z[idx], xv = A.x[idx], dl = A.denom[idx];
+        const float sv = fmaf(rho, A.G[idx], (1.0f - rho) * A.g[idx]);
+        const float num = fmaf(rho * dl, zv - xv, sv) + reg_grad_at<IS3D>(K, A.z, i, j, k, A.beta, A.inv_delta2);
+        const float den = fmaf(rho, dl, A.beta * reg_curv_sum(K, i, j, k));
+        v = zv;
+        if (den > 0.0f) {
+            v = zv - num / den;
+            if (A.nonneg) v = fmaxf(v, 0.0f);
+        }
+        if (LAST) {
+            A.x[idx] = v;
+            const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
+                                         : ((long long)j * K.ldN + i + 2);
+            A.XN[n_idx] = v;
+        } else {
+            const float vp = A.v[idx];
+            A.v[idx] = v;
+            A.zout[idx] = fmaf(A.mom, v - vp, v);
+        }
+    }
+    if (!LAST) return;
+    tile[ty][tx] = v;
+    __syncthreads();
+    const int it = blockIdx.x * 32 + ty, jt = blockIdx.y * 32 + tx;
+    if (it < K.nx && jt < K.ny) {
+        const long long t_idx = IS3D ? ((long long)it * K.slabT + (long long)(k + 2) * K.ldT + jt + 2)
+                                     : ((long long)it * K.ldT + jt + 2);
+        A.XT[t_idx] = tile[tx][ty];
     }
 }
 
@@ -341,7 +413,8 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
 }
 
 hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
-                         const float *denom, float beta, int nonneg, const ContArgs *cont, hipStream_t st)
+                         const float *denom, float beta, int nonneg, const ContArgs *cont, hipStream_t st,
+                         float *vout, float *zout)
 {
     UpdArgs a;
     a.k = p->k;
@@ -361,9 +434,42 @@ hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G,
     a.sc_out = p->d_sc + (p->sc_cur ^ 1);
     if (a.do_finalize) a.cont = *cont;
     else a.cont = ContArgs{};
+    a.vout = mode == UPD_STEP ? vout : nullptr;
+    a.zout = mode == UPD_STEP ? zout : nullptr;
     hipError_t e = p->is3d ? upd_dispatch<true>(a, mode, st) : upd_dispatch<false>(a, mode, st);
     if (a.do_finalize) p->sc_cur ^= 1;
     return e;
+}
+
+hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zout, float *x, const float *G,
+                        const float *g, const float *denom, float beta, float inv_delta2, float mom, int nonneg,
+                        bool last, hipStream_t st)
+{
+    InnerArgs a;
+    a.k = p->k;
+    a.z = z;
+    a.G = G;
+    a.g = g;
+    a.denom = denom;
+    a.v = v;
+    a.zout = zout;
+    a.x = x;
+    a.XT = p->d_xt;
+    a.XN = p->d_xn;
+    a.sc = cur_sc(p);
+    a.beta = beta;
+    a.inv_delta2 = inv_delta2;
+    a.mom = mom;
+    a.nonneg = nonneg;
+    dim3 blk(32, 32), grd((p->nx + 31) / 32, (p->ny + 31) / 32, p->nz);
+    if (p->is3d) {
+        if (last) hipLaunchKernelGGL((inner_kernel<true, true>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((inner_kernel<true, false>), grd, blk, 0, st, a);
+    } else {
+        if (last) hipLaunchKernelGGL((inner_kernel<false, true>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((inner_kernel<false, false>), grd, blk, 0, st, a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,

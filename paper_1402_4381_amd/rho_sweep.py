@@ -13,7 +13,9 @@ the synthetic 2D fan-beam workload with the library's own kernels:
   order, RMSD to x* after every iteration;
 * acceleration of rho over rho = 1 at a level R: iterations rho = 1 needs to
   reach R divided by the iterations rho needs (rho = 1 runs long enough to
-  reach the levels that matter).
+  reach the levels that matter);
+* the continuation with n = 2 and 5 inner FISTA iterations (Sec. IV-A: the
+  paper finds the gain from n > 1 slight), with the time per iteration.
 """
 import argparse
 import json
@@ -25,7 +27,7 @@ import numpy as np
 
 
 def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=600, xstar_iters=6000,
-        seed=None, dev="cuda:0"):
+        seed=None, inners=(2, 5), dev="cuda:0"):
     import torch
     import synth
     from paper_1402_4381_amd import lalm
@@ -64,14 +66,22 @@ def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=6
     plan = lalm.lalm_plan_geometry(geom, M)
     y, w, d = problem(plan)
     curves = {}
-    for name, cont, rho, n in [("continuation", True, 1.0, iters)] + \
-            [("rho=%g" % r, False, r, iters_rho1 if r == 1.0 else iters) for r in rhos]:
+    runs = [("continuation", True, 1.0, iters, 1)] + \
+        [("continuation n=%d" % ni, True, 1.0, iters, ni) for ni in inners] + \
+        [("rho=%g" % r, False, r, iters_rho1 if r == 1.0 else iters, 1) for r in rhos]
+    wall = {}
+    for name, cont, rho, n, ni in runs:
         st = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
         hist = []
+        t_run = 0.0
         for _ in range(n):
-            lalm.lalm_iterate(plan, y, w, d, beta, delta, st, M, continuation=cont, rho_fixed=rho)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            lalm.lalm_iterate(plan, y, w, d, beta, delta, st, M, continuation=cont, rho_fixed=rho, n_inner=ni)
+            t_run += time.perf_counter() - t1
             hist.append(round(rmsd(plan, st.x, xs.x), 4))
         curves[name] = hist
+        wall[name] = round(t_run / n * 1e3, 3)
         print("%-13s RMSD after 10/30/%d iterations: %.2f / %.2f / %.2f HU"
               % (name, n, hist[9], hist[29], hist[-1]), flush=True)
 
@@ -91,7 +101,7 @@ def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=6
     iters_to = {name: {"%g" % L: first_below(h, L) for L in levels} for name, h in curves.items()}
     return dict(workload=workload, M=M, xstar_iters=xstar_iters, xstar_last100_change_hu=round(change, 5),
                 iterations_to_level=iters_to, acceleration_over_rho1=accel,
-                rmsd_hu_at_30={k: v[29] for k, v in curves.items()}, curves=curves)
+                rmsd_hu_at_30={k: v[29] for k, v in curves.items()}, ms_per_iteration=wall, curves=curves)
 
 
 def main(argv=None):

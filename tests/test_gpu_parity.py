@@ -186,20 +186,20 @@ def test_sqs_denominator_and_cost(L, name, over, M):
     assert abs(c[0] - cr[0]) <= 1e-4 * abs(cr[0])
 
 
-def _run_both(L, cfg, M, n_iter, continuation=True, rho_fixed=1.0, seed=None):
+def _run_both(L, cfg, M, n_iter, continuation=True, rho_fixed=1.0, seed=None, n_inner=1):
     data = _problem(cfg, seed)
     beta = cfg["beta"]
     delta = synth.configs.delta_mu(cfg)
     n_steps = n_iter * M
     ref = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=n_steps,
-                      continuation=continuation, rho_fixed=rho_fixed)
+                      continuation=continuation, rho_fixed=rho_fixed, n_inner=n_inner)
     plan, y, w, denom = _gpu_problem(L, cfg, M, data)
     st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
     stats = dict(rho=torch.zeros(n_steps, dtype=torch.float64, device=DEV),
                  xi=torch.zeros(n_steps, dtype=torch.float64, device=DEV),
                  restart=torch.zeros(n_steps, dtype=torch.uint8, device=DEV))
     L.lalm_iterate(plan, y, w, denom, beta, delta, st, n_steps, continuation=continuation,
-                   rho_fixed=rho_fixed, stats=stats)
+                   rho_fixed=rho_fixed, stats=stats, n_inner=n_inner)
     return data, ref, plan, (y, w, denom, beta, delta), st, stats
 
 
@@ -308,6 +308,28 @@ def test_full_size_sampled_parity(L, name, M, n_vox):
     assert ebp <= 1e-5
 
 
+@pytest.mark.parametrize("name,over,M,n_iter,n_inner", [("fan2d_128", {}, 4, 10, 2), ("fan2d_128", {}, 4, 10, 5),
+                                                        ("cone_axial_512x64", MED3D, 5, 3, 3)])
+def test_os_lalm_parity_inner_fista(L, name, over, M, n_iter, n_inner):
+    """n_inner FISTA iterations on the inner problem (Sec. IV-A) against the
+    oracle's, free-running; the inner iterates differ from n = 1, so the
+    image must too."""
+    cfg = synth.get_config(name, **over)
+    if over:
+        data = _problem(cfg)
+        dl = ora.sqs_denom(cfg, data["w"])
+        cfg["beta"] = synth.configs.BETA_REL * float(np.median(dl[synth.roi_mask(cfg)]))
+    data, ref, plan, prob, st, stats = _run_both(L, cfg, M, n_iter, n_inner=n_inner)
+    d, mism, rs, xi = _report(cfg, ref, st, stats)
+    one = ora.os_lalm(cfg, data["y"], data["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=M,
+                      n_steps=n_iter * M)
+    gap = ora.rmsd_hu(one["x"], ref["x"], synth.roi_mask(cfg), synth.HU_PER_MU)
+    say("%s n_inner=%d: RMSD to oracle %.2e HU, restart mismatches %d / %d; n=1 vs n=%d differ by %.3f HU"
+        % (name, n_inner, d, mism, len(rs), n_inner, gap))
+    assert d <= 0.5
+    assert gap > 10 * max(d, 1e-3)
+
+
 def test_fixed_rho_parity(L):
     cfg = synth.get_config("fan2d_128")
     data, ref, plan, prob, st, stats = _run_both(L, cfg, 4, 10, continuation=False, rho_fixed=0.1)
@@ -390,8 +412,9 @@ def test_edge_cases(L):
         assert torch.count_nonzero(st.grad) > 0
         L.lalm_iterate(plan, y, w, denom, 1e-3, 2e-4, st, 2 * M)
         assert st.step == 2 * M and torch.isfinite(st.x).all()
-    with pytest.raises(L.LalmError):
-        L.lalm_iterate(plan, y, w, denom, 1e-3, 2e-4, st, 1, n_inner=2)
+    for bad in (0, 17):
+        with pytest.raises(L.LalmError):
+            L.lalm_iterate(plan, y, w, denom, 1e-3, 2e-4, st, 1, n_inner=bad)
     with pytest.raises(L.LalmError):
         L.lalm_project_subset(plan, M, torch.zeros(plan.image_elems, device=DEV),
                               torch.zeros(16, device=DEV))
