@@ -367,9 +367,22 @@ def inner_fista(x, s, DL, DR, rho, beta, delta, is3d, n, nonneg=True):
     return v_prev
 
 
+def bb_alpha(s, yv, DL, alpha_min):
+    """Barzilai-Borwein scale of the SQS Hessian (supplement, eq.
+    "scale_factor_alpha_k"): alpha = argmin_{alpha <= 1} 1/2 ||y - alpha L s||^2_P
+    with P = L^-1 and L = D_L, i.e. <s, y> / <s, L s> capped at 1.  Readings:
+    a non-positive <s, y> or <s, L s> (no curvature information) gives 1, and
+    alpha is kept at or above alpha_min."""
+    sy = float(np.sum(s * yv))
+    sls = float(np.sum(DL * s * s))
+    if not (sy > 0.0 and sls > 0.0):
+        return 1.0
+    return min(1.0, max(alpha_min, sy / sls))
+
+
 def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0,
             rho_min=1e-3, x0=None, denom=None, forced_restart=None, nonneg=True,
-            callback=None, n_inner=1):
+            callback=None, n_inner=1, bb=False, bb_alpha_min=0.01):
     """OS-LALM, Sec. III-A eq. "os_lalm_iterates".
 
     The substitution of eq. "ct_substitution" makes grad l_m the weighted
@@ -379,6 +392,14 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     (:func:`inner_fista`); n_inner = 1 is one projected gradient step with
     the diagonal majorizer rho D_L + D_R (the first FISTA step has no
     momentum).
+
+    bb: the Barzilai-Borwein acceleration of the supplement, H_k = alpha_k
+    D_L in place of D_L.  Readings: k counts iterations (M subset steps);
+    alpha_k (:func:`bb_alpha`) is computed at the start of iteration k >= 1
+    from s = x - x_prev and y = G - G_prev, the images and the scaled
+    gradients M grad l_{order[0]} held at the starts of iterations k and
+    k - 1 (the same subset, so y is a gradient difference), and is used for
+    the M steps of iteration k; alpha_0 = 1.
 
     Step j (0-based) visits subset order[(j + 1) mod M] for the gradient at
     the new image; the initial gradient is G = M grad l_{order[0]}(x0) and
@@ -403,13 +424,20 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     g = G.copy()
     l = 0
     rho = 1.0 if continuation else rho_fixed
-    hist_rho, hist_xi, hist_rs = [], [], []
+    hist_rho, hist_xi, hist_rs, hist_alpha = [], [], [], []
+    alpha, x_prev, G_prev = 1.0, None, None
     for j in range(n_steps):
+        if bb and j % M == 0:
+            if j > 0:
+                alpha = bb_alpha(x - x_prev, G - G_prev, DL, bb_alpha_min)
+            x_prev, G_prev = x.copy(), G.copy()
+        H = alpha * DL
         s = rho * G + (1.0 - rho) * g
         if n_inner == 1:
-            x_new = _xstep(x, s + reg_grad(x, beta, delta, is3d), rho * DL + DR, nonneg)
+            x_new = _xstep(x, s + reg_grad(x, beta, delta, is3d), rho * H + DR, nonneg)
         else:
-            x_new = inner_fista(x, s, DL, DR, rho, beta, delta, is3d, n_inner, nonneg)
+            x_new = inner_fista(x, s, H, DR, rho, beta, delta, is3d, n_inner, nonneg)
+        hist_alpha.append(alpha)
         G_new = subset_gradient(cfg, x_new, y, w, subsets[order[(j + 1) % M]], M)
         g_new = (rho * G_new + g) / (rho + 1.0)
         xi = float(np.sum((g - G_new) * (G_new - G)))
@@ -427,7 +455,7 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
         if callback is not None:
             callback(j, x)
     return dict(x=x, g=g, G=G, rho=np.array(hist_rho), xi=np.array(hist_xi),
-                restart=np.array(hist_rs), l=l, next_rho=rho)
+                restart=np.array(hist_rs), l=l, next_rho=rho, alpha=np.array(hist_alpha))
 
 
 def fista_restart(cfg, y, w, beta, delta, x0, n_iter, denom=None, nonneg=True):

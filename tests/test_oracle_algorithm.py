@@ -322,3 +322,51 @@ def test_os_lalm_n_inner_one_matches_the_default():
     a = ora.os_lalm(cfg, d["y"], d["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=3, n_steps=6)
     b = ora.os_lalm(cfg, d["y"], d["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=3, n_steps=6, n_inner=1)
     assert np.array_equal(a["x"], b["x"])
+
+
+# ---------------------------------------------------------------- Barzilai-Borwein scale
+
+def test_bb_alpha_is_the_constrained_weighted_least_squares_fit():
+    """alpha = argmin_{alpha <= 1} 1/2 ||y - alpha L s||^2_{L^-1}, checked by a
+    bounded scalar minimization of that objective (independent of the closed
+    form), for a fit below 1 and one capped at 1."""
+    from scipy.optimize import minimize_scalar
+    rng = np.random.default_rng(3)
+    L = rng.uniform(0.5, 3.0, 200)
+    s = rng.normal(size=200)
+    for scale in (0.3, 4.0):
+        yv = scale * L * s + rng.normal(0.0, 0.05, 200)
+        obj = lambda a: 0.5 * np.sum((yv - a * L * s) ** 2 / L)
+        ref = minimize_scalar(obj, bounds=(-10.0, 1.0), method="bounded", options=dict(xatol=1e-12)).x
+        got = ora.bb_alpha(s, yv, L, 1e-3)
+        assert got == pytest.approx(ref, abs=1e-6)
+    assert ora.bb_alpha(s, -L * s, L, 1e-3) == 1.0               # no curvature information
+    assert ora.bb_alpha(s, 1e-6 * L * s, L, 0.01) == 0.01        # floor
+
+
+def test_bb_on_a_quadratic_fits_the_curvature_along_the_step():
+    """One subset, beta = 0: y = A'WA s exactly, so alpha is the Rayleigh
+    quotient s'A'WA s / s'D_L s of the step (below 1 because D_L majorizes
+    A'WA), and the run records it from the second iteration on."""
+    cfg = synth.get_config("tiny2d")
+    d = synth.make_problem_data(cfg, workers=1)
+    DL = ora.sqs_denom(cfg, d["w"])
+    r = ora.os_lalm(cfg, d["y"], d["w"], 0.0, synth.configs.delta_mu(cfg), M=1, n_steps=4,
+                    continuation=False, rho_fixed=1.0, bb=True, denom=DL)
+    assert r["alpha"][0] == 1.0
+    a = r["alpha"][1:]
+    assert np.all((a > 0.0) & (a <= 1.0)) and np.any(a < 0.999)
+    # alpha_1 recomputed from the first two iterates by the Rayleigh quotient
+    r1 = ora.os_lalm(cfg, d["y"], d["w"], 0.0, synth.configs.delta_mu(cfg), M=1, n_steps=1,
+                     continuation=False, rho_fixed=1.0, denom=DL)
+    s = r1["x"] - np.zeros_like(r1["x"])
+    Ad = ora.forward(cfg, s)
+    rq = float(np.sum(d["w"] * Ad * Ad)) / float(np.sum(DL * s * s))
+    assert a[0] == pytest.approx(rq, rel=1e-9)
+
+
+def test_os_lalm_without_bb_is_unchanged():
+    cfg = synth.get_config("tiny2d")
+    d = synth.make_problem_data(cfg, workers=1)
+    a = ora.os_lalm(cfg, d["y"], d["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=3, n_steps=6)
+    assert np.all(a["alpha"] == 1.0)
