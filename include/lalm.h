@@ -169,12 +169,18 @@ typedef struct {
  * l and rho are the continuation counter and the rho of the next step.  When
  * step == 0, lalm_iterate initializes grad = g = M grad l_{order[0]}(x),
  * l = 0 and rho = 1 (continuation) or rho_fixed.  The struct is updated on
- * return, so a state saved after a call resumes bit-exactly. */
+ * return, so a state saved after a call resumes bit-exactly.
+ * Barzilai-Borwein history (used only with lalm_options.bb = 1, else may be
+ * null / ignored): x_prev, grad_prev are device images holding x and grad at
+ * the start of the current iteration (written by the library at every
+ * iteration start), alpha the current scale of D_L (set to 1 at step 0). */
 typedef struct {
     float *x, *g, *grad;
     int64_t step;
     int64_t l;
     double rho;
+    float *x_prev, *grad_prev;
+    double alpha;
 } lalm_state;
 
 /* continuation: 1 = downward continuation with adaptive restart (Sec. III-B),
@@ -185,7 +191,13 @@ typedef struct {
  * gradient step (the paper's default), n > 1 costs n - 1 more image passes
  * with a regularizer gradient each.  forced_restart: optional DEVICE array of
  * forced_len bytes indexed by global step; when step < forced_len its value
- * replaces the restart test (replay of a restart sequence). */
+ * replaces the restart test (replay of a restart sequence).
+ * bb = 1: Barzilai-Borwein acceleration (supplement, eq.
+ * scale_factor_alpha_k): the majorizer D_L is replaced by alpha_k D_L with
+ * alpha_k = min(1, <s, y> / <s, D_L s>) (FP64), s and y the differences of
+ * the image and of the scaled gradient M grad l_{order[0]} between the
+ * starts of iterations k and k - 1 (every M steps); alpha_k >= bb_alpha_min,
+ * and 1 when <s, y> <= 0.  Needs state.x_prev and state.grad_prev. */
 #define LALM_MAX_INNER 16
 
 typedef struct {
@@ -194,6 +206,8 @@ typedef struct {
     int32_t n_inner;
     const uint8_t *forced_restart;
     int64_t forced_len;
+    int32_t bb;
+    double bb_alpha_min;
 } lalm_options;
 
 /* Optional per-step record, DEVICE arrays indexed by global step (entries at

@@ -132,6 +132,15 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     if (s->step < 0) return fail(LALM_E_STATE, "lalm_iterate: negative state step");
     if (s->step > 0 && (s->l < 0 || !(s->rho > 0.0) || !std::isfinite(s->rho)))
         return fail(LALM_E_STATE, "lalm_iterate: inconsistent continuation state");
+    if (opt->bb) {
+        if (!s->x_prev || !s->grad_prev) return fail(LALM_E_INVALID, "lalm_iterate: bb needs state.x_prev and state.grad_prev");
+        if (!(opt->bb_alpha_min > 0.0 && opt->bb_alpha_min <= 1.0))
+            return fail(LALM_E_INVALID, "lalm_iterate: bb_alpha_min must lie in (0, 1]");
+        if (s->step > 0 && !(s->alpha > 0.0 && s->alpha <= 1.0))
+            return fail(LALM_E_STATE, "lalm_iterate: inconsistent Barzilai-Borwein state");
+    }
+    if (p->n_partials < p->bp_nblocks + 2 * 1024 || p->n_partials < 4096)
+        return fail(LALM_E_STATE, "lalm_iterate: reduction workspace too small");
 
     const int M = p->M;
     const float beta = (float)prob->beta;
@@ -157,7 +166,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     }
 
     if (s->step == 0) {
-        HIPCHK("iterate scalars", launch_set_scalars(p, 0, opt->continuation ? 1.0 : opt->rho_fixed, 0, st));
+        HIPCHK("iterate scalars", launch_set_scalars(p, 0, opt->continuation ? 1.0 : opt->rho_fixed, 0, 1.0, st));
         HIPCHK("iterate layout", launch_update(p, UPD_LAYOUT, s->x, nullptr, nullptr, nullptr, 0.0f, 0, nullptr, st));
         const int m0 = p->order[0];
         HIPCHK("iterate init project", launch_fp(p, subset_slot0(p, m0), subset_nview(p, m0),
@@ -167,7 +176,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
                                                      BP_INIT, e, st));
     } else {
         const double rho = opt->continuation ? s->rho : opt->rho_fixed;
-        HIPCHK("iterate scalars", launch_set_scalars(p, s->l, rho, s->step, st));
+        HIPCHK("iterate scalars", launch_set_scalars(p, s->l, rho, s->step, opt->bb ? s->alpha : 1.0, st));
         HIPCHK("iterate resume", launch_reg_grad(p, s->x, beta, inv_delta2, st));
     }
     // The continuation decision after a step's back-projection is taken by
@@ -178,6 +187,9 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     for (int64_t t = 0; t < n_steps; ++t) {
         const int64_t j = s->step + t;
         const int m = p->order[(size_t)((j + 1) % M)];
+        if (opt->bb && j % M == 0)
+            HIPCHK("iterate bb", launch_bb(p, s->x, s->grad, s->x_prev, s->grad_prev, prob->denom, j > 0,
+                                           opt->bb_alpha_min, st));
         {
             ProfScope ps(p, 0, st);
             const int n = opt->n_inner;
@@ -219,6 +231,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     s->step = p->h_sc->step;
     s->l = p->h_sc->l;
     s->rho = p->h_sc->rho;
+    s->alpha = p->h_sc->alpha;
     if (p->h_sc->status)
         return fail(LALM_E_NONFINITE, "lalm_iterate: non-finite restart indicator; later steps skipped");
     return LALM_OK;

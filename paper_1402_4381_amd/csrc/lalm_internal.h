@@ -52,6 +52,7 @@ struct DevScalars {
     long long step;   // global subset-step counter
     int status;       // 0 ok, 1 non-finite restart indicator met
     int pad;
+    double alpha;     // Barzilai-Borwein scale of D_L (1 without it)
 };
 
 // Geometry constants handed to kernels by value.
@@ -279,8 +280,13 @@ hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zou
                         bool last, hipStream_t st);
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,
                            hipStream_t st);
-hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,
+hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step, double alpha,
                               hipStream_t st);
+// Barzilai-Borwein step at an iteration start: with compute, alpha in the
+// current scalar record from s = x - x_prev, y = grad - grad_prev (FP64,
+// fixed order); then x_prev, grad_prev <- x, grad.
+hipError_t launch_bb(const lalm_plan *p, const float *x, const float *grad, float *x_prev, float *grad_prev,
+                     const float *denom, bool compute, double alpha_min, hipStream_t st);
 
 // FP64 reductions
 hipError_t launch_sum_partials(const double *part, int64_t n, double *out, double scale,

@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         const float rho = (float)s.rho;
         if (inside) {
             const float num = fmaf(rho, Gv, (1.0f - rho) * gv) + rv;
-            const float den = fmaf(rho, dv, A.beta * reg_curv_sum(K, i, j, k));
+            const float den = fmaf(rho * (float)s.alpha, dv, A.beta * reg_curv_sum(K, i, j, k));
             if (den > 0.0f) {
                 v = v - num / den;
                 if (A.nonneg) v = fmaxf(v, 0.0f);
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(1024) inner_kernel(InnerArgs A)
     float v = 0.0f;
     if (inside) {
         const long long idx = ((long long)k * K.ny + j) * K.nx + i;
-        const float zv = A.z[idx], xv = A.x[idx], dl = A.denom[idx];
+        const float zv = A.z[idx], xv = A.x[idx], dl = (float)s.alpha * A.denom[idx];
         const float sv = fmaf(rho, A.G[idx], (1.0f - rho) * A.g[idx]);
         const float num = fmaf(rho * dl, zv - xv, sv) + reg_grad_at<IS3D>(K, A.z, i, j, k, A.beta, A.inv_delta2);
         const float den = fmaf(rho, dl, A.beta * reg_curv_sum(K, i, j, k));
@@ -372,7 +372,7 @@ hipError_t upd_dispatch(const UpdArgs &a, int mode, hipStream_t st)
     return hipGetLastError();
 }
 
-__global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long long step)
+__global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long long step, double alpha)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         sc->rho = rho;
@@ -381,7 +381,59 @@ __global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long
         sc->step = step;
         sc->status = 0;
         sc->pad = 0;
+        sc->alpha = alpha;
     }
+}
+
+// ---------------------------------------------------------------- Barzilai-Borwein
+//
+// <s, y> and <s, D_L s> with s = x - x_prev, y = grad - grad_prev, per block
+// in FP64 (grid-stride, fixed order), then x_prev, grad_prev <- x, grad.
+constexpr int BB_BLOCKS = 1024;
+
+__global__ void __launch_bounds__(256) bb_dot_kernel(const float *x, const float *grad, float *xp, float *gp,
+                                                     const float *denom, long long n, int compute, double *part)
+{
+    __shared__ double s_w[2][4];
+    const int tid = threadIdx.x;
+    double sy = 0.0, sls = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + tid; i < n; i += (long long)gridDim.x * 256) {
+        const float xv = x[i], gv = grad[i];
+        if (compute) {
+            const double sv = (double)xv - (double)xp[i];
+            sy += sv * ((double)gv - (double)gp[i]);
+            sls += (double)denom[i] * sv * sv;
+        }
+        xp[i] = xv;
+        gp[i] = gv;
+    }
+    if (!compute) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sy += __shfl_xor(sy, o, 64);
+        sls += __shfl_xor(sls, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        s_w[0][tid >> 6] = sy;
+        s_w[1][tid >> 6] = sls;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        part[blockIdx.x] = (s_w[0][0] + s_w[0][1]) + (s_w[0][2] + s_w[0][3]);
+        part[BB_BLOCKS + blockIdx.x] = (s_w[1][0] + s_w[1][1]) + (s_w[1][2] + s_w[1][3]);
+    }
+}
+
+// alpha = min(1, <s,y> / <s,D_L s>), at least alpha_min; 1 without curvature
+// information (non-positive sums).  Written into the current scalar record.
+__global__ void __launch_bounds__(256) bb_finalize_kernel(const double *part, DevScalars *sc, double alpha_min)
+{
+    __shared__ double s_w[4];
+    if (sc->status) return;
+    const int tid = threadIdx.x;
+    const double sy = fixed_sum_256(part, BB_BLOCKS, tid, s_w);
+    const double sls = fixed_sum_256(part + BB_BLOCKS, BB_BLOCKS, tid, s_w);
+    if (tid == 0) sc->alpha = (sy > 0.0 && sls > 0.0) ? fmin(1.0, fmax(alpha_min, sy / sls)) : 1.0;
 }
 
 }  // namespace
@@ -472,10 +524,23 @@ hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zou
     return hipGetLastError();
 }
 
-hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step,
+hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step, double alpha,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, cur_sc(p), l, rho, step);
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, cur_sc(p), l, rho, step, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_bb(const lalm_plan *p, const float *x, const float *grad, float *x_prev, float *grad_prev,
+                     const float *denom, bool compute, double alpha_min, hipStream_t st)
+{
+    // the last 2 x BB_BLOCKS partial slots, above any back-projection's block partials
+    double *part = p->d_partials + p->n_partials - 2 * BB_BLOCKS;
+    const long long n = (long long)p->nx * p->ny * p->nz;
+    hipLaunchKernelGGL(bb_dot_kernel, dim3(BB_BLOCKS), dim3(256), 0, st, x, grad, x_prev, grad_prev, denom, n,
+                       compute ? 1 : 0, part);
+    if (compute) hipLaunchKernelGGL(bb_finalize_kernel, dim3(1), dim3(256), 0, st, (const double *)part, cur_sc(p),
+                                    alpha_min);
     return hipGetLastError();
 }
 

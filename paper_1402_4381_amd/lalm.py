@@ -51,13 +51,15 @@ class Problem(ctypes.Structure):
 
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("g", ctypes.c_void_p), ("grad", ctypes.c_void_p),
-                ("step", ctypes.c_int64), ("l", ctypes.c_int64), ("rho", ctypes.c_double)]
+                ("step", ctypes.c_int64), ("l", ctypes.c_int64), ("rho", ctypes.c_double),
+                ("x_prev", ctypes.c_void_p), ("grad_prev", ctypes.c_void_p), ("alpha", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("continuation", ctypes.c_int32), ("rho_fixed", ctypes.c_double),
                 ("rho_min", ctypes.c_double), ("n_inner", ctypes.c_int32),
-                ("forced_restart", ctypes.c_void_p), ("forced_len", ctypes.c_int64)]
+                ("forced_restart", ctypes.c_void_p), ("forced_len", ctypes.c_int64),
+                ("bb", ctypes.c_int32), ("bb_alpha_min", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -258,34 +260,43 @@ def _problem(plan, y, w, denom, beta, delta, nonneg):
 
 
 class LalmState:
-    """Caller-owned iteration state: GPU images x, g, grad and the scalars."""
+    """Caller-owned iteration state: GPU images x, g, grad, the scalars and,
+    for the Barzilai-Borwein option, the images at the start of the current
+    iteration (x_prev, grad_prev) and the scale alpha."""
 
-    def __init__(self, x, g, grad, step=0, l=0, rho=1.0):
+    def __init__(self, x, g, grad, step=0, l=0, rho=1.0, x_prev=None, grad_prev=None, alpha=1.0):
         self.x, self.g, self.grad = x, g, grad
         self.step, self.l, self.rho = int(step), int(l), float(rho)
+        self.x_prev, self.grad_prev, self.alpha = x_prev, grad_prev, float(alpha)
 
     @classmethod
-    def zeros_like(cls, x):
+    def zeros_like(cls, x, bb=False):
         import torch
-        return cls(x, torch.zeros_like(x), torch.zeros_like(x))
+        z = torch.zeros_like
+        return cls(x, z(x), z(x), x_prev=z(x) if bb else None, grad_prev=z(x) if bb else None)
 
     def clone(self):
-        return LalmState(self.x.clone(), self.g.clone(), self.grad.clone(), self.step, self.l, self.rho)
+        c = lambda t: None if t is None else t.clone()
+        return LalmState(self.x.clone(), self.g.clone(), self.grad.clone(), self.step, self.l, self.rho,
+                         c(self.x_prev), c(self.grad_prev), self.alpha)
 
 
 def lalm_iterate(plan, y, w, denom, beta, delta, state, n_steps, continuation=True,
                  rho_fixed=1.0, rho_min=1e-3, n_inner=1, nonneg=True, forced_restart=None,
-                 stats=None, stream=None):
+                 stats=None, stream=None, bb=False, bb_alpha_min=0.01):
     """Run ``n_steps`` subset steps; ``state`` (LalmState) is updated in place.
     ``stats``: optional dict of GPU tensors rho (float64), xi (float64),
     restart (uint8) indexed by global step.  ``forced_restart``: optional
     uint8 GPU tensor indexed by global step."""
     prob = _problem(plan, y, w, denom, beta, delta, nonneg)
     st = State(_dev(state.x, "x", numel=plan.image_elems), _dev(state.g, "g", numel=plan.image_elems),
-               _dev(state.grad, "grad", numel=plan.image_elems), state.step, state.l, state.rho)
+               _dev(state.grad, "grad", numel=plan.image_elems), state.step, state.l, state.rho,
+               _dev(state.x_prev, "x_prev", numel=plan.image_elems, allow_none=True),
+               _dev(state.grad_prev, "grad_prev", numel=plan.image_elems, allow_none=True), state.alpha)
     fr = _dev(forced_restart, "forced_restart", dtype="uint8", allow_none=True)
     opt = Options(1 if continuation else 0, float(rho_fixed), float(rho_min), int(n_inner), fr,
-                  int(forced_restart.numel()) if forced_restart is not None else 0)
+                  int(forced_restart.numel()) if forced_restart is not None else 0,
+                  1 if bb else 0, float(bb_alpha_min))
     sp = None
     if stats is not None:
         cap = min(stats["rho"].numel(), stats["xi"].numel(), stats["restart"].numel())
@@ -294,7 +305,7 @@ def lalm_iterate(plan, y, w, denom, beta, delta, state, n_steps, continuation=Tr
                                 _dev(stats["restart"], "stats.restart", dtype="uint8"), cap))
     status = _lib.lalm_iterate(plan.handle, ctypes.byref(prob), ctypes.byref(st), int(n_steps),
                                ctypes.byref(opt), sp, _stream(stream))
-    state.step, state.l, state.rho = st.step, st.l, st.rho
+    state.step, state.l, state.rho, state.alpha = st.step, st.l, st.rho, st.alpha
     _check(status)
     return state
 

@@ -15,7 +15,9 @@ the synthetic 2D fan-beam workload with the library's own kernels:
   reach R divided by the iterations rho needs (rho = 1 runs long enough to
   reach the levels that matter);
 * the continuation with n = 2 and 5 inner FISTA iterations (Sec. IV-A: the
-  paper finds the gain from n > 1 slight), with the time per iteration.
+  paper finds the gain from n > 1 slight), and with the Barzilai-Borwein
+  scaling of D_L (supplement: about 2x in early iterations), with the time
+  per iteration.
 """
 import argparse
 import json
@@ -66,18 +68,19 @@ def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=6
     plan = lalm.lalm_plan_geometry(geom, M)
     y, w, d = problem(plan)
     curves = {}
-    runs = [("continuation", True, 1.0, iters, 1)] + \
-        [("continuation n=%d" % ni, True, 1.0, iters, ni) for ni in inners] + \
-        [("rho=%g" % r, False, r, iters_rho1 if r == 1.0 else iters, 1) for r in rhos]
+    runs = [("continuation", True, 1.0, iters, 1, False), ("continuation bb", True, 1.0, iters, 1, True)] + \
+        [("continuation n=%d" % ni, True, 1.0, iters, ni, False) for ni in inners] + \
+        [("rho=%g" % r, False, r, iters_rho1 if r == 1.0 else iters, 1, False) for r in rhos]
     wall = {}
-    for name, cont, rho, n, ni in runs:
-        st = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+    for name, cont, rho, n, ni, bb in runs:
+        st = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev), bb=bb)
         hist = []
         t_run = 0.0
         for _ in range(n):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            lalm.lalm_iterate(plan, y, w, d, beta, delta, st, M, continuation=cont, rho_fixed=rho, n_inner=ni)
+            lalm.lalm_iterate(plan, y, w, d, beta, delta, st, M, continuation=cont, rho_fixed=rho, n_inner=ni,
+                              bb=bb)
             t_run += time.perf_counter() - t1
             hist.append(round(rmsd(plan, st.x, xs.x), 4))
         curves[name] = hist

@@ -330,6 +330,36 @@ def test_os_lalm_parity_inner_fista(L, name, over, M, n_iter, n_inner):
     assert gap > 10 * max(d, 1e-3)
 
 
+@pytest.mark.parametrize("name,over,M,n_iter", [("fan2d_128", {}, 4, 12), ("cone_axial_512x64", MED3D, 5, 4)])
+def test_os_lalm_parity_bb(L, name, over, M, n_iter):
+    """Barzilai-Borwein scaling of D_L (supplement) against the oracle:
+    images within 0.5 HU, the scale alpha of the last iteration to 1e-4, and
+    splitting the run over two calls (the history lives in the caller's
+    state) is bit-identical to one call."""
+    cfg = synth.get_config(name, **over)
+    data = _problem(cfg)
+    if over:
+        dl = ora.sqs_denom(cfg, data["w"])
+        cfg["beta"] = synth.configs.BETA_REL * float(np.median(dl[synth.roi_mask(cfg)]))
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    n_steps = n_iter * M
+    ref = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=n_steps, bb=True)
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV), bb=True)
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st, n_steps, bb=True)
+    d = ora.rmsd_hu(st.x.cpu().numpy().reshape(ora.image_shape(cfg)), ref["x"], synth.roi_mask(cfg),
+                    synth.HU_PER_MU)
+    say("%s bb: RMSD %.2e HU, alpha gpu %.6f oracle %.6f (alphas %s)"
+        % (name, d, st.alpha, ref["alpha"][-1], np.unique(np.round(ref["alpha"], 4))))
+    assert d <= 0.5
+    assert abs(st.alpha - ref["alpha"][-1]) <= 1e-4 * ref["alpha"][-1]
+    assert ref["alpha"][-1] < 0.999
+    st2 = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV), bb=True)
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st2, n_steps // 2 + 1, bb=True)
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st2, n_steps - (n_steps // 2 + 1), bb=True)
+    assert torch.equal(st.x, st2.x) and st.alpha == st2.alpha
+
+
 def test_fixed_rho_parity(L):
     cfg = synth.get_config("fan2d_128")
     data, ref, plan, prob, st, stats = _run_both(L, cfg, 4, 10, continuation=False, rho_fixed=0.1)
