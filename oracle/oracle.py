@@ -612,3 +612,64 @@ def rmsd_hu(a, b, mask, hu_per_mu):
     """RMS difference over the ROI, in HU (Sec. V)."""
     d = (np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64))[mask]
     return float(np.sqrt(np.mean(d * d)) * hu_per_mu)
+
+
+# ------------------------------------------------------------- FBP (x0)
+
+def fbp_fan(cfg, sino):
+    """Filtered back-projection for the 2D equiangular (arc-detector) fan
+    beam over a full turn, the initial image the paper's experiments start
+    from (figure captions).  The paper gives no formula; this is the textbook
+    equiangular fan-beam reconstruction (reading): cosine-weighted data
+    q = p D cos(gamma); the fan-beam ramp kernel
+    g(n dgamma) = 1/2 (n dgamma / sin(n dgamma))^2 h(n dgamma) with the
+    band-limited (Ram-Lak) ramp h(0) = 1/(4 dgamma^2), h(odd n) =
+    -1/(n pi dgamma)^2, h(even n != 0) = 0; Q = dgamma (q * g); and
+    f(P) = dbeta sum_views Q(gamma'(P)) / L(P)^2, with L the distance from
+    the source to P and gamma'(P) the fan angle of the ray through P, Q
+    interpolated linearly in channel (zero off the detector).
+
+    sino: natural-order [n_views][1][n_bins] (or [n_views][n_bins]) line
+    integrals.  Returns [1][ny][nx]."""
+    if cfg["kind"] != 0 or cfg["n_views"] != cfg["n_views_per_turn"]:
+        raise ValueError("fbp_fan: 2D fan beam over one full turn only")
+    nb, nv = cfg["n_bins"], cfg["n_views"]
+    p = np.asarray(sino, dtype=np.float64).reshape(nv, nb)
+    dg = cfg["ds"] / cfg["dsd"]
+    D = cfg["dso"]
+    gam = (np.arange(nb) - (nb - 1) / 2.0 - cfg["channel_offset"]) * dg
+    q = p * (D * np.cos(gam))[None, :]
+    n = np.arange(-(nb - 1), nb)
+    h = np.zeros(n.shape)
+    h[n == 0] = 1.0 / (4.0 * dg * dg)
+    odd = (n % 2) != 0
+    h[odd] = -1.0 / (n[odd] * np.pi * dg) ** 2
+    ratio = np.ones(n.shape)
+    nz = n != 0
+    ratio[nz] = (n[nz] * dg) / np.sin(n[nz] * dg)
+    g = 0.5 * ratio * ratio * h
+    Q = np.empty_like(q)
+    for v in range(nv):
+        Q[v] = dg * np.convolve(q[v], g)[nb - 1:2 * nb - 1]
+    nx, ny = cfg["nx"], cfg["ny"]
+    X = (np.arange(nx) - (nx - 1) / 2.0) * cfg["dx"]
+    Y = (np.arange(ny) - (ny - 1) / 2.0) * cfg["dy"]
+    PX, PY = np.meshgrid(X, Y)
+    dbeta = 2.0 * np.pi / cfg["n_views_per_turn"]
+    f = np.zeros((ny, nx))
+    for v in range(nv):
+        beta = cfg["start_angle"] + 2.0 * np.pi * v / cfg["n_views_per_turn"]
+        sx, sy = D * np.cos(beta), D * np.sin(beta)
+        dx_, dy_ = PX - sx, PY - sy
+        along = -(dx_ * np.cos(beta) + dy_ * np.sin(beta))       # towards the isocentre
+        perp = dx_ * np.sin(beta) - dy_ * np.cos(beta)           # central ray rotated +90 deg
+        gp = np.arctan2(perp, along)
+        bc = gp / dg + (nb - 1) / 2.0 + cfg["channel_offset"]
+        b0 = np.floor(bc).astype(np.int64)
+        t = bc - b0
+        val = np.zeros_like(bc)
+        for bb, wgt in ((b0, 1.0 - t), (b0 + 1, t)):
+            ok = (bb >= 0) & (bb < nb)
+            val[ok] += wgt[ok] * Q[v, bb[ok]]
+        f += dbeta * val / (dx_ * dx_ + dy_ * dy_)
+    return f[None]
