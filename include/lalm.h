@@ -151,6 +151,15 @@ LALM_API lalm_status lalm_backproject_subset(lalm_plan *plan, int32_t m, const f
  */
 LALM_API lalm_status lalm_sqs_denom(lalm_plan *plan, const float *w_full, float *denom, hipStream_t stream);
 
+/* Initial image by filtered back-projection (the paper's experiments start
+ * from an FBP image; figure captions): textbook equiangular fan-beam FBP of
+ * the line integrals y_full (device, subset-major like lalm_iterate's y;
+ * rays with zero counts carry y = 0) into x_out (device [ny][nx]): cosine
+ * weighting, the fan-beam Ram-Lak kernel, 1/L^2-weighted back-projection
+ * with linear interpolation in channel, FP32.  2D fan beam over one full
+ * turn only; LALM_E_INVALID otherwise or for more than 4096 channels. */
+LALM_API lalm_status lalm_fbp(lalm_plan *plan, const float *y_full, float *x_out, hipStream_t stream);
+
 /* The PWLS problem of Sec. IV: data, weights, SQS denominator, and the
  * hyperbola edge-preserving regularizer
  *   R(x) = beta sum_{pairs j~k} kappa_jk psi(x_j - x_k),

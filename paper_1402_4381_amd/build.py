@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "liblalm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["plan.hip", "project.hip", "backproject.hip", "reduce.hip", "api.hip", "unet.hip"]
+SOURCES = ["plan.hip", "project.hip", "backproject.hip", "reduce.hip", "api.hip", "unet.hip", "fbp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

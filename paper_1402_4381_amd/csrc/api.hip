@@ -116,6 +116,16 @@ extern "C" lalm_status lalm_sqs_denom(lalm_plan *p, const float *w_full, float *
     return LALM_OK;
 }
 
+extern "C" lalm_status lalm_fbp(lalm_plan *p, const float *y_full, float *x_out, hipStream_t st)
+{
+    if (!p || !y_full || !x_out) return fail(LALM_E_INVALID, "lalm_fbp: null argument");
+    if (p->is3d || p->g.n_views != p->g.n_views_per_turn)
+        return fail(LALM_E_INVALID, "lalm_fbp: 2D fan beam over one full turn only");
+    if (p->nb > fbp_max_bins()) return fail(LALM_E_INVALID, "lalm_fbp: too many channels");
+    HIPCHK("fbp", launch_fbp(p, y_full, x_out, st));
+    return LALM_OK;
+}
+
 extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm_state *s,
                                     int64_t n_steps, const lalm_options *opt, const lalm_stats *stats,
                                     hipStream_t st)

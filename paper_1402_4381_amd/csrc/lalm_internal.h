@@ -209,6 +209,7 @@ struct lalm_plan {
     float *d_part = nullptr;            // 2D: back-projection of the x-dominant rays
     float *d_part2 = nullptr;           // 2D: back-projection of the y-dominant rays
     float *d_v = nullptr;               // inner FISTA iterate (n_inner > 1); part, part2 hold z
+    float *d_fbpq = nullptr;            // 2D: filtered sinogram of the FBP
     double *d_partials = nullptr;       // reduction partials
     int64_t n_partials = 0;
     // two device scalar records: each continuation decision reads one and
@@ -287,6 +288,10 @@ hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long 
 // fixed order); then x_prev, grad_prev <- x, grad.
 hipError_t launch_bb(const lalm_plan *p, const float *x, const float *grad, float *x_prev, float *grad_prev,
                      const float *denom, bool compute, double alpha_min, hipStream_t st);
+
+// FBP of a full-turn 2D fan-beam sinogram (subset-major y) into x.
+hipError_t launch_fbp(const lalm_plan *p, const float *y, float *x, hipStream_t st);
+int fbp_max_bins();
 
 // FP64 reductions
 hipError_t launch_sum_partials(const double *part, int64_t n, double *out, double scale,

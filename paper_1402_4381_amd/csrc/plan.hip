@@ -87,6 +87,7 @@ static void free_plan(lalm_plan *p)
     (void)hipFree(p->d_xn);
     (void)hipFree(p->d_gradR);
     (void)hipFree(p->d_v);
+    (void)hipFree(p->d_fbpq);
     (void)hipFree(p->d_r);
     (void)hipFree(p->d_part);
     (void)hipFree(p->d_part2);
@@ -291,6 +292,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(dev_alloc(&p->d_part, nvox));
     chk(dev_alloc(&p->d_part2, nvox));
     chk(dev_alloc(&p->d_v, nvox));
+    if (!is3d) chk(dev_alloc(&p->d_fbpq, (size_t)p->nv * p->nb));
     chk(dev_alloc(&p->d_partials, (size_t)p->n_partials));
     chk(dev_alloc(&p->d_sc, 2));
     chk(dev_alloc(&p->d_tmp, (size_t)(64 + M)));

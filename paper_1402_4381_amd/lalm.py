@@ -21,7 +21,7 @@ FAN2D, CONE_AXIAL, CONE_HELICAL = 0, 1, 2
 
 EXPORTS = ("lalm_last_error", "lalm_version", "lalm_plan_geometry", "lalm_plan_info",
            "lalm_plan_destroy", "lalm_project_subset", "lalm_backproject_subset",
-           "lalm_sqs_denom", "lalm_iterate", "lalm_cost_f64", "lalm_dot_f64",
+           "lalm_sqs_denom", "lalm_fbp", "lalm_iterate", "lalm_cost_f64", "lalm_dot_f64",
            "lalm_roi_rmsd_f64", "lalm_profile_begin", "lalm_profile_read",
            "lalm_profile_end", "lalm_unet_param_count", "lalm_unet_create",
            "lalm_unet_destroy", "lalm_unet_forward", "lalm_unet_loss_grad", "lalm_unet_adam")
@@ -82,6 +82,7 @@ def _load():
         "lalm_project_subset": ([P, I32, P, P, P, P, P], I32),
         "lalm_backproject_subset": ([P, I32, P, P, F32, I32, P], I32),
         "lalm_sqs_denom": ([P, P, P, P], I32),
+        "lalm_fbp": ([P, P, P, P], I32),
         "lalm_iterate": ([P, ctypes.POINTER(Problem), ctypes.POINTER(State), I64,
                           ctypes.POINTER(Options), ctypes.POINTER(Stats), P], I32),
         "lalm_cost_f64": ([P, ctypes.POINTER(Problem), P, P, P], I32),
@@ -251,6 +252,11 @@ def lalm_backproject_subset(plan, m, r, x_out, scale=1.0, accumulate=False, stre
 def lalm_sqs_denom(plan, w_full, denom, stream=None):
     _check(_lib.lalm_sqs_denom(plan.handle, _dev(w_full, "w_full", numel=plan.sino_elems),
                                _dev(denom, "denom", numel=plan.image_elems), _stream(stream)))
+
+
+def lalm_fbp(plan, y_full, x_out, stream=None):
+    _check(_lib.lalm_fbp(plan.handle, _dev(y_full, "y_full", numel=plan.sino_elems),
+                         _dev(x_out, "x_out", numel=plan.image_elems), _stream(stream)))
 
 
 def _problem(plan, y, w, denom, beta, delta, nonneg):

@@ -360,6 +360,33 @@ def test_os_lalm_parity_bb(L, name, over, M, n_iter):
     assert torch.equal(st.x, st2.x) and st.alpha == st2.alpha
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name", ["fan2d_128", "fan2d_512"])
+def test_fbp_parity(L, name):
+    """GPU FBP of the noisy data against the oracle's (same textbook
+    equiangular fan-beam formula in FP64): relative L2 <= 1e-4 and max error
+    <= 1e-4 x max (FP32 filtering sums ~ n_bins terms of both signs)."""
+    cfg = synth.get_config(name)
+    data = _problem(cfg)
+    ref = ora.fbp_fan(cfg, data["y"])
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), cfg["M"])
+    y = gpu(data["y"][plan.view_of_slot]).reshape(-1)
+    x = torch.empty(plan.image_elems, device=DEV)
+    L.lalm_fbp(plan, y, x)
+    got = x.cpu().numpy().reshape(ref.shape)
+    e = rel_l2(got, ref)
+    emax = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  fbp %s: rel L2 %.2e, max %.2e" % (name, e, emax))
+    assert e <= 1e-4 and emax <= 1e-4
+
+
+def test_fbp_rejects_cone_beam(L):
+    cfg = synth.get_config("tiny3d")
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), 2)
+    with pytest.raises(L.LalmError):
+        L.lalm_fbp(plan, torch.zeros(plan.sino_elems, device=DEV), torch.zeros(plan.image_elems, device=DEV))
+
+
 def test_fixed_rho_parity(L):
     cfg = synth.get_config("fan2d_128")
     data, ref, plan, prob, st, stats = _run_both(L, cfg, 4, 10, continuation=False, rho_fixed=0.1)
