@@ -484,6 +484,184 @@ hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------
+// Weight gradient dW[m][n] = sum_k A[k][m] B[k][n] over pixels k (split K):
+// A = the output gradient dz (channels m; A_MC, or its 2x2 phase ab of a 2x
+// grid), B = the input at the tap of column n (B_NC).  Same MFMA layout as
+// gemm_kernel.  Every thread keeps the pixel of each of its slots as
+// (image row r = b*H + y, y, x) and steps it by BK pixels per K step, and
+// the tap / channel / source of each B slot is fixed for the kernel, so the
+// K loop does no integer division.  Two pixels per thread and slot are
+// loaded, so the transposing LDS stores write packed pairs.
+struct PixState {
+    int r, y, x, k;
+};
+
+__device__ inline PixState pix_init(int k, int H, int W)
+{
+    PixState p;
+    p.k = k;
+    p.r = k / W;
+    p.x = k - p.r * W;
+    p.y = p.r % H;
+    return p;
+}
+
+__device__ inline void pix_advance(PixState &p, int by, int H, int W)
+{
+    p.k += by;
+    p.x += by;
+    while (p.x >= W) {
+        p.x -= W;
+        ++p.r;
+        if (++p.y == H) p.y = 0;
+    }
+}
+
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
+{
+    static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32x32");
+    constexpr int PA = BM * BK / 16;                 // A pixel pairs x channel vectors in the tile
+    constexpr int PB = BN * BK / 16;
+    constexpr int NA = (PA + 255) / 256, NB = (PB + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv % (BM / 32), wn = wv / (BM / 32);
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int kbeg = blockIdx.z * g.klen, kend = min(g.K, kbeg + g.klen);
+    const int H = g.gH, W = g.gW;
+
+    // A slots: pixel pair kp (pixels 2kp, 2kp+1 of the tile), channels mv..mv+7
+    PixState pa[NA][2];
+    int am[NA];
+    bool aon[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) {
+        const int s = tid + 256 * v;
+        aon[v] = PA % 256 == 0 || s < PA;
+        const int kp = s / (BM / 8);
+        am[v] = m0 + (s % (BM / 8)) * 8;
+        pa[v][0] = pix_init(kbeg + 2 * kp, H, W);
+        pa[v][1] = pix_init(kbeg + 2 * kp + 1, H, W);
+    }
+    // B slots: the column block fixes the tap, channel and source
+    PixState pb[NB][2];
+    const bf16 *bsrc[NB];
+    int bcs[NB], bcc[NB], bdy[NB], bdx[NB];
+    bool bon[NB];
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+        const int s = tid + 256 * v;
+        const int kp = s / (BN / 8), n = n0 + (s % (BN / 8)) * 8;
+        bon[v] = (PB % 256 == 0 || s < PB) && n < g.N;
+        const int cin = g.bc1 + g.bc2;
+        const int tap = bon[v] ? n / cin : 0, c = bon[v] ? n - tap * cin : 0;
+        bdy[v] = g.bntap == 9 ? tap / 3 - 1 : 0;
+        bdx[v] = g.bntap == 9 ? tap % 3 - 1 : 0;
+        const bool first = c < g.bc1;
+        bsrc[v] = first ? g.b1 : g.b2;
+        bcs[v] = first ? g.bc1 : g.bc2;
+        bcc[v] = first ? c : c - g.bc1;
+        pb[v][0] = pix_init(kbeg + 2 * kp, H, W);
+        pb[v][1] = pix_init(kbeg + 2 * kp + 1, H, W);
+    }
+
+    auto load_a2 = [&](bf16x8 (*ra)[2]) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const PixState &p = pa[v][h];
+                bf16x8 r = zero8();
+                if (aon[v] && p.k < kend && am[v] < g.M) {
+                    const long long pix = g.ab >= 0 ? (long long)(2 * p.r + (g.ab >> 1)) * (2 * W) + 2 * p.x + (g.ab & 1)
+                                                    : (long long)p.k;
+                    r = ld8(g.a1 + pix * g.ac1 + am[v]);
+                }
+                ra[v][h] = r;
+            }
+    };
+    auto load_b2 = [&](bf16x8 (*rb)[2]) {
+#pragma unroll
+        for (int v = 0; v < NB; ++v)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const PixState &p = pb[v][h];
+                const int yy = p.y + bdy[v], xx = p.x + bdx[v];
+                bf16x8 r = zero8();
+                if (bon[v] && p.k < kend && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
+                    r = ld8(bsrc[v] + ((long long)(p.r + bdy[v]) * W + xx) * bcs[v] + bcc[v]);
+                rb[v][h] = r;
+            }
+    };
+    auto advance = [&]() {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            pix_advance(pa[v][0], BK, H, W);
+            pix_advance(pa[v][1], BK, H, W);
+        }
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            pix_advance(pb[v][0], BK, H, W);
+            pix_advance(pb[v][1], BK, H, W);
+        }
+    };
+    // transposed stores: element i of the two pixels' vectors -> one 32-bit word
+    auto store2 = [&](bf16 *S, int per_row, int n_pairs, int s, const bf16x8 &v0, const bf16x8 &v1) {
+        if (s >= n_pairs) return;
+        const int kp = s / (per_row / 8), mv = (s % (per_row / 8)) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+            bf16x2 pr;
+            pr[0] = v0[i];
+            pr[1] = v1[i];
+            *reinterpret_cast<bf16x2 *>(S + (mv + i) * LDK + 2 * kp) = pr;
+        }
+    };
+
+    bf16x8 ra[NA][2], rb[NB][2];
+    floatx16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    int buf = 0;
+    if (kbeg < kend) {
+        load_a2(ra);
+        load_b2(rb);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) store2(As[buf], BM, PA, tid + 256 * v, ra[v][0], ra[v][1]);
+#pragma unroll
+        for (int v = 0; v < NB; ++v) store2(Bs[buf], BN, PB, tid + 256 * v, rb[v][0], rb[v][1]);
+        __syncthreads();
+        if (k0 + BK < kend) {                      // prefetch the next tile
+            advance();
+            load_a2(ra);
+            load_b2(rb);
+        }
+        const bf16 *as = As[buf] + (wm * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
+        const bf16 *bs = Bs[buf] + (wn * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(as + kk);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(bs + kk);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        buf ^= 1;
+    }
+    const int col = n0 + wn * 32 + (lane & 31);
+    if (col >= g.N) return;
+    float *dst = g.part + (long long)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int m = m0 + wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+        if (m < g.M) dst[(long long)m * g.N + col] = acc[t];
+    }
+}
+
 // 3x3 convolutions with 32 output channels take the patch-staged kernel
 // (its weights for 32 channels fit beside the patch); wider outputs keep
 // the generic implicit GEMM, whose smaller LDS footprint keeps more blocks
@@ -947,8 +1125,8 @@ hipError_t wgrad_gemm(lalm_unet *n, GemmArgs &g, float *dst, hipStream_t st)
     ns = (g.K + g.klen - 1) / g.klen;
     g.part = n->part;
     const dim3 grd(gx, gy, (unsigned)ns);
-    if (narrow) hipLaunchKernelGGL((gemm_kernel<A_MC, B_NC, E_WG, 32, 128>), grd, dim3(256), 0, st, g);
-    else hipLaunchKernelGGL((gemm_kernel<A_MC, B_NC, E_WG, 64, 64>), grd, dim3(256), 0, st, g);
+    if (narrow) hipLaunchKernelGGL((wgrad_kernel<32, 128>), grd, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((wgrad_kernel<64, 64>), grd, dim3(256), 0, st, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long cnt = (long long)g.M * g.N;
@@ -1135,7 +1313,7 @@ extern "C" lalm_status lalm_unet_create(int32_t batch_max, int32_t height, int32
     chk(alloc(n, &n->lpart, (size_t)(P / 256 + 1)));
     // partial sums: weight-gradient splits (the split count adapts to this
     // size) and per-chunk column sums
-    n->part_elems = std::max<int64_t>(256LL * 128 * 1152, (P / 4096 + 1) * 320);
+    n->part_elems = std::max<int64_t>(256LL * 128 * 1152, (P / 1024 + 1) * 320);
     chk(alloc(n, &n->part, (size_t)n->part_elems));
     if (e != hipSuccess) {
         std::string m = std::string("lalm_unet_create: allocation failed: ") + hipGetErrorString(e);
@@ -1278,7 +1456,8 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     UCHK("e1a dz", to_dz(n->gA, n->e1a, dz2, P * 32, st));
     std::swap(dz, dz2);
     {
-        const int chunk = 4096, ns = (int)((P + chunk - 1) / chunk);
+        // 1024 pixels per block: enough blocks to fill the chip at every batch size
+        const int chunk = 1024, ns = (int)((P + chunk - 1) / chunk);
         hipLaunchKernelGGL(conv1_wgrad_kernel, dim3(ns), dim3(256), 0, st, x, (float)in_scale, dz, n->part, B, H, W,
                            chunk);
         // part[s][c*10 + t] -> weights [c][t] (t < 9) and bias [c]
