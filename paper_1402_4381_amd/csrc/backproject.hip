@@ -54,10 +54,13 @@ __device__ inline double block_sum_256(double v, double *lds)
     return t;   // valid in thread 0
 }
 
-template <bool IS3D, int MODE>
+// 3D back-projection, voxel driven (the 2D one is the line kernel below):
+// each thread gathers KZ3 slices of one (x, y) column from every ray of
+// the subset whose Joseph taps land on them, then applies the epilogue.
+template <int MODE>
 __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 {
-    constexpr int KZ = IS3D ? KZ3 : 1;
+    constexpr int KZ = KZ3;
     const GeoK &K = A.k;
     if (MODE != BP_PLAIN && A.sc->status) return;
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -68,10 +71,8 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 
     __shared__ float s_rowv[256], s_rowf[256];
     __shared__ double s_red[4];
-    if (IS3D) {
-        for (int t = tid; t < K.nr; t += 256) { s_rowv[t] = A.rowv[t]; s_rowf[t] = A.rowf[t]; }
-        __syncthreads();
-    }
+    for (int t = tid; t < K.nr; t += 256) { s_rowv[t] = A.rowv[t]; s_rowf[t] = A.rowf[t]; }
+    __syncthreads();
 
     float acc[KZ];
 #pragma unroll
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
         const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
         for (int kv = 0; kv < A.nview; ++kv) {
             const ViewRec V = A.views[kv];
-            if (IS3D) {
+            {
                 const float tmax = sqrtf((bxc - V.sx) * (bxc - V.sx) + (byc - V.sy) * (byc - V.sy)) + bhd;
                 const float reach = fmaf(K.zreach, tmax, 1.01f);
                 if ((float)kb > V.z0 + reach || (float)(kb + KZ - 1) < V.z0 - reach) continue;
@@ -114,9 +115,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                 const int j0 = (int)fl;
                 const float wxy = (j0 == o) ? (1.0f - f) : ((j0 + 1 == o) ? f : 0.0f);
                 if (wxy == 0.0f) continue;
-                if (!IS3D) {
-                    acc[0] = fmaf(wxy * rr.sc, A.r[(long long)kv * K.nb + b], acc[0]);
-                } else {
+                {
                     const RayRecZ rz = A.raysz[(long long)kv * K.nb + b];
                     const float qz = fmaf((float)s, rz.k, rz.m);
                     const float inv = K.inv_dt / qz;     // detector rows per slice
@@ -160,7 +159,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                 const float Gv = A.e.scale * acc[t];
                 A.e.G[idx] = Gv;
                 A.e.g[idx] = Gv;
-                A.e.out[idx] = reg_grad_at<IS3D>(K, A.e.x, i, j, k, A.e.beta, inv_delta2);
+                A.e.out[idx] = reg_grad_at<true>(K, A.e.x, i, j, k, A.e.beta, inv_delta2);
                 part += (double)Gv * (double)Gv;
             } else {
                 const float Gn = A.e.scale * acc[t];
@@ -168,7 +167,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                 part += ((double)gv - (double)Gn) * ((double)Gn - (double)Go);
                 A.e.g[idx] = fmaf(rho, Gn, gv) / (rho + 1.0f);
                 A.e.G[idx] = Gn;
-                A.e.out[idx] = reg_grad_at<IS3D>(K, A.e.x, i, j, k, A.e.beta, inv_delta2);
+                A.e.out[idx] = reg_grad_at<true>(K, A.e.x, i, j, k, A.e.beta, inv_delta2);
             }
         }
     }
@@ -424,13 +423,12 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, l
     if (tid == 0) *out = continuation_update(s, C, total, MODE == BP_INIT, true);
 }
 
-template <bool IS3D>
 hipError_t bp_dispatch(const BPArgs &a, int mode, dim3 grd, hipStream_t st)
 {
     dim3 blk(32, 8);
-    if (mode == BP_PLAIN) hipLaunchKernelGGL((bp_kernel<IS3D, BP_PLAIN>), grd, blk, 0, st, a);
-    else if (mode == BP_INIT) hipLaunchKernelGGL((bp_kernel<IS3D, BP_INIT>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((bp_kernel<IS3D, BP_STEP>), grd, blk, 0, st, a);
+    if (mode == BP_PLAIN) hipLaunchKernelGGL((bp_kernel<BP_PLAIN>), grd, blk, 0, st, a);
+    else if (mode == BP_INIT) hipLaunchKernelGGL((bp_kernel<BP_INIT>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((bp_kernel<BP_STEP>), grd, blk, 0, st, a);
     return hipGetLastError();
 }
 
@@ -477,7 +475,7 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
         const int kz = KZ3;
         dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + kz - 1) / kz);
         a.nblocks = (int)(grd.x * grd.y * grd.z);
-        hipError_t e = bp_dispatch<true>(a, mode, grd, st);
+        hipError_t e = bp_dispatch(a, mode, grd, st);
         if (e != hipSuccess) return e;
     }
     if (mode == BP_PLAIN) return hipGetLastError();
