@@ -5,7 +5,10 @@ One step = one OS-LALM subset iteration of the whole hot path: x-update
 (regularizer majorizer, continuation rho), forward projection of the next
 subset with fused weighted residual, matched back-projection with the fused
 g-update, regularizer gradient and FP64 restart indicator, and the
-continuation decision.  The workload is the 512^2 fan-beam problem
+continuation decision.  In 2D the back-projection epilogue and the next
+x-update are one kernel (it computes the next x for both values the pending
+decision can give rho; the forward projection takes the decision and reads
+the chosen one).  The workload is the 512^2 fan-beam problem
 (984 views x 888 bins, M = 24 subsets, 40-ellipse seeded phantom, Poisson
 counts at I0 = 5e4); all inputs are resident in GPU memory before timing.
 
@@ -25,18 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = {"project": "paper_1402_4381_amd/csrc/project.hip",
-                  "backproject": "paper_1402_4381_amd/csrc/backproject.hip",
-                  "update": "paper_1402_4381_amd/csrc/project.hip"}
+# sources of each kernel class (2D: the update class is the fused step kernel)
+_CSRC = "paper_1402_4381_amd/csrc/"
+KERNEL_SOURCES = {"project": [_CSRC + "project.hip", _CSRC + "lalm_internal.h"],
+                  "backproject": [_CSRC + "backproject.hip", _CSRC + "lalm_internal.h"],
+                  "update": [_CSRC + "backproject.hip", _CSRC + "project.hip", _CSRC + "lalm_internal.h"]}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash(rel):
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(rels):
+    h = hashlib.sha256()
+    for rel in rels:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel, workload):
@@ -212,7 +220,14 @@ def main():
     lalm.lalm_profile_end(plan)
     avg_ms = ms / np.maximum(cnt, 1)
 
-    # algorithmic bytes per launch, averaged over the subsets the steps visit
+    # algorithmic bytes per launch, averaged over the subsets the steps visit.
+    # 2D: the back-projection class is the line kernel (taps, residual, the
+    # two partial images written); the update class is the step kernel that
+    # fuses the back-projection epilogue with the next x-update (reads the
+    # partial images, G, g, x, D_L; writes G, g, x and both x candidates
+    # with their two projector layouts).  3D: the voxel-driven kernel with
+    # its epilogue (G, g, x read; G, g, grad R written), and the x-update.
+    fused = cfg["kind"] == 0
     taps = 4 if cfg["kind"] != 0 else 2
     nvox = plan.image_elems
     fp_b = bp_b = 0.0
@@ -221,10 +236,10 @@ def main():
         s = float(plan.subset_samples[m])
         rays = float(plan.subset_rays(m))
         fp_b += s * taps * 4 + rays * 12          # taps + y, w read + residual write
-        bp_b += s * taps * 4 + rays * 4 + nvox * 24   # taps + residual + G, g, x read; G, g, grad R write
+        bp_b += s * taps * 4 + rays * 4 + nvox * (8 if fused else 24)
     fp_b /= args.steps
     bp_b /= args.steps
-    upd_b = nvox * 32.0
+    upd_b = nvox * (60.0 if fused else 32.0)
     kern = {"update": (avg_ms[0], upd_b), "project": (avg_ms[1], fp_b), "backproject": (avg_ms[2], bp_b)}
     dom = max(kern, key=lambda k: kern[k][0])
     t_ms, b = kern[dom]

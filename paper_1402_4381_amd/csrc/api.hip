@@ -30,30 +30,17 @@ lalm_status hip_fail(const char *where, hipError_t e)
 
 int64_t subset_slot0(const lalm_plan *p, int m) { return p->slot_offset[m]; }
 
-// Event pairs around the kernels of lalm_iterate when profiling is on.
+// Opens a kernel class of lalm_iterate while profiling: the kernels that
+// are launched until it closes are timed and attributed to it.
 struct ProfScope {
     lalm_plan *p;
-    hipStream_t st;
-    int kind;
-    hipEvent_t stop = nullptr;
-    ProfScope(lalm_plan *p_, int kind_, hipStream_t st_) : p(p_), st(st_), kind(kind_)
+    ProfScope(lalm_plan *p_, int kind, hipStream_t) : p(p_)
     {
         if (!p->prof) return;
-        if (p->prof_used + 2 > p->prof_ev.size()) {
-            size_t n = p->prof_ev.size();
-            p->prof_ev.resize(std::max<size_t>(64, 2 * n));
-            for (size_t i = n; i < p->prof_ev.size(); ++i) (void)hipEventCreate(&p->prof_ev[i]);
-        }
-        hipEvent_t start = p->prof_ev[p->prof_used];
-        stop = p->prof_ev[p->prof_used + 1];
-        p->prof_used += 2;
-        p->prof_kind.push_back(kind);
-        (void)hipEventRecord(start, st);
+        p->prof_cls = kind;
+        p->prof_n[kind] += 1;
     }
-    ~ProfScope()
-    {
-        if (stop) (void)hipEventRecord(stop, st);
-    }
+    ~ProfScope() { p->prof_cls = -1; }
 };
 
 // After a stream synchronization: fold recorded pairs into the totals.
@@ -62,10 +49,8 @@ void prof_collect(lalm_plan *p)
     if (!p->prof) return;
     for (size_t k = 0; k < p->prof_kind.size(); ++k) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, p->prof_ev[2 * k], p->prof_ev[2 * k + 1]) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, p->prof_ev[2 * k], p->prof_ev[2 * k + 1]) == hipSuccess)
             p->prof_ms[p->prof_kind[k]] += ms;
-            p->prof_n[p->prof_kind[k]] += 1;
-        }
     }
     p->prof_kind.clear();
     p->prof_used = 0;
@@ -191,16 +176,28 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     }
     // The continuation decision after a step's back-projection is taken by
     // a one-block kernel, or in 2D by the next step's x-update kernel
-    // (fused: every block reduces the epilogue's partials; 3D has too many
+    // (fused: every wave reduces the epilogue's partials; 3D has too many
     // partials for that).  No decision stays pending between calls.
+    //
+    // 2D with n = 1 and no Barzilai-Borwein scaling, within a call: the
+    // step kernel after the back-projection also computes the next x for
+    // both values the pending decision can give rho (restart or continue),
+    // into one of two candidate pairs; the next forward projection takes
+    // the decision and reads the chosen candidate's layouts, and the next
+    // step kernel reads that candidate (and copies it to the caller's x).
+    // Same arithmetic as the unfused path, one kernel fewer per step.
+    const bool fused = !p->is3d && opt->n_inner == 1 && !opt->bb && n_steps >= 2;
+    const size_t nvox = (size_t)p->nx * p->ny * p->nz;
     bool pending = false;
     for (int64_t t = 0; t < n_steps; ++t) {
         const int64_t j = s->step + t;
         const int m = p->order[(size_t)((j + 1) % M)];
+        const bool f_in = fused && t > 0;             // x of this step is a candidate
+        const bool f_out = fused && t + 1 < n_steps;  // this step makes the next candidates
         if (opt->bb && j % M == 0)
             HIPCHK("iterate bb", launch_bb(p, s->x, s->grad, s->x_prev, s->grad_prev, prob->denom, j > 0,
                                            opt->bb_alpha_min, st));
-        {
+        if (!f_in) {
             ProfScope ps(p, 0, st);
             const int n = opt->n_inner;
             // FISTA on the inner problem: iteration 1 is the projected step
@@ -222,17 +219,37 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
         }
         {
             ProfScope ps(p, 1, st);
-            HIPCHK("iterate project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m),
-                                                prob->y + subset_ray0(p, m), prob->w + subset_ray0(p, m),
-                                                p->d_r, 0, 0, nullptr, 1, st));
+            if (f_in)
+                HIPCHK("iterate project", launch_fp_decide(p, subset_slot0(p, m), subset_nview(p, m),
+                                                           prob->y + subset_ray0(p, m),
+                                                           prob->w + subset_ray0(p, m), p->d_r, e.cont, st));
+            else
+                HIPCHK("iterate project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m),
+                                                    prob->y + subset_ray0(p, m), prob->w + subset_ray0(p, m),
+                                                    p->d_r, 0, 0, nullptr, 1, st));
         }
-        {
+        if (!fused) {
             ProfScope ps(p, 2, st);
             HIPCHK("iterate backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r,
                                                     BP_STEP, e, st));
             if (p->is3d) HIPCHK("iterate finalize", launch_finalize(p, e.cont, st));
             else pending = true;
+            continue;
         }
+        {
+            ProfScope ps(p, 2, st);
+            HIPCHK("iterate backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r,
+                                                    BP_LINES, e, st));
+        }
+        {
+            ProfScope ps(p, 0, st);
+            const float *xs = f_in ? p->d_xc + (size_t)((t - 1) % 2) * 2 * nvox : s->x;
+            float *xo = p->d_xc + (size_t)(t % 2) * 2 * nvox;
+            HIPCHK("iterate step", launch_step2d(p, xs, f_in ? xs + nvox : s->x, f_in ? s->x : nullptr,
+                                                 f_out ? xo : nullptr, f_out ? xo + nvox : nullptr, e,
+                                                 prob->denom, prob->nonneg, !f_out, st));
+        }
+        pending = true;
     }
     if (pending) HIPCHK("iterate finalize", launch_finalize(p, e.cont, st));
     HIPCHK("iterate readback", hipMemcpyAsync(p->h_sc, cur_sc(p), sizeof(DevScalars), hipMemcpyDeviceToHost, st));

@@ -367,7 +367,8 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
 }
 
 // Pointwise epilogue of the 2D back-projection: total = part_x + part_y, then
-// PLAIN (out = scale * total, or +=), INIT or STEP as in the 3D kernel.
+// PLAIN (out = scale * total, or +=) or INIT as in the 3D kernel (STEP is
+// the step kernel below).
 template <int MODE>
 __global__ void __launch_bounds__(256) bp2d_epilogue_kernel(BPArgs A)
 {
@@ -383,20 +384,12 @@ __global__ void __launch_bounds__(256) bp2d_epilogue_kernel(BPArgs A)
         if (MODE == BP_PLAIN) {
             const float vv = A.e.scale * total;
             A.e.out[idx] = A.e.accumulate ? A.e.out[idx] + vv : vv;
-        } else if (MODE == BP_INIT) {
+        } else {
             const float Gv = A.e.scale * total;
             A.e.G[idx] = Gv;
             A.e.g[idx] = Gv;
             A.e.out[idx] = reg_grad_at<false>(K, A.e.x, i, j, 0, A.e.beta, A.e.inv_delta2);
             part = (double)Gv * (double)Gv;
-        } else {
-            const float rho = (float)A.sc->rho;
-            const float Gn = A.e.scale * total;
-            const float Go = A.e.G[idx], gv = A.e.g[idx];
-            part = ((double)gv - (double)Gn) * ((double)Gn - (double)Go);
-            A.e.g[idx] = fmaf(rho, Gn, gv) / (rho + 1.0f);
-            A.e.G[idx] = Gn;
-            A.e.out[idx] = reg_grad_at<false>(K, A.e.x, i, j, 0, A.e.beta, A.e.inv_delta2);
         }
     }
     if (MODE == BP_PLAIN) return;
@@ -405,10 +398,108 @@ __global__ void __launch_bounds__(256) bp2d_epilogue_kernel(BPArgs A)
     if (threadIdx.x + 32 * threadIdx.y == 0) A.partials[blin] = bsum;
 }
 
+// 2D step epilogue, fused with the next step's x-update (one thread per
+// pixel of a 32x32 tile).  G+ = M (part + part2); the restart-indicator
+// partial (g - G+)(G+ - G) in FP64; g <- (rho G+ + g) / (rho + 1); G <- G+.
+// x of this step is xs[sel].  Not LAST: the next step's x for each value
+// its rho can take once the pending decision is made (candidate 0: restart,
+// rho_0 = 1, or the fixed rho; candidate 1: continue, rho_{l+1}), written
+// to xo and to the layout set of the candidate (XN directly, XT through an
+// LDS transpose).  LAST: grad R(x) instead, as the plain epilogue.  Block
+// partial: wave butterflies, then the 16 wave sums in order.
+struct Step2dArgs {
+    GeoK k;
+    const float *part, *part2;
+    float *G, *g;
+    const float *xs0, *xs1;
+    float *xw;
+    const float *denom;
+    float *gradR;
+    float *xo0, *xo1, *XT0, *XN0, *XT1, *XN1;
+    const DevScalars *sc;
+    double *partials;
+    float scale, beta, inv_delta2;
+    double rho_min;
+    int continuation, nonneg;
+};
+
+template <bool LAST>
+__global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
+{
+    const GeoK &K = A.k;
+    const DevScalars s = *A.sc;
+    if (s.status) return;
+    __shared__ float tile[2][32][33];
+    __shared__ double s_red[16];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + 32 * ty;
+    const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
+    const bool inside = i < K.nx && j < K.ny;
+    const float *xs = s.sel ? A.xs1 : A.xs0;
+    const float rho = (float)s.rho;
+    const bool two = A.continuation != 0;
+    double part = 0.0;
+    float v0 = 0.0f, v1 = 0.0f;
+    if (inside) {
+        const long long idx = (long long)j * K.nx + i;
+        const float total = A.part[idx] + A.part2[idx];
+        const float Gn = A.scale * total;
+        const float Go = A.G[idx], gv = A.g[idx];
+        part = ((double)gv - (double)Gn) * ((double)Gn - (double)Go);
+        const float gn = fmaf(rho, Gn, gv) / (rho + 1.0f);
+        A.G[idx] = Gn;
+        A.g[idx] = gn;
+        const float rv = reg_grad_at<false>(K, xs, i, j, 0, A.beta, A.inv_delta2);
+        const float xv = xs[idx];
+        if (A.xw) A.xw[idx] = xv;
+        if (LAST) {
+            A.gradR[idx] = rv;
+        } else {
+            const float dv = A.denom[idx];
+            const float curv = A.beta * reg_curv_sum(K, i, j, 0);
+            const float alpha = (float)s.alpha;
+            const long long n_idx = (long long)j * K.ldN + i + 2;
+            v0 = x_update(xv, Gn, gn, rv, two ? 1.0f : rho, alpha, dv, curv, A.nonneg);
+            A.xo0[idx] = v0;
+            A.XN0[n_idx] = v0;
+            if (two) {
+                const float r1 = (float)continuation_rho(s.l + 1, A.rho_min);
+                v1 = x_update(xv, Gn, gn, rv, r1, alpha, dv, curv, A.nonneg);
+                A.xo1[idx] = v1;
+                A.XN1[n_idx] = v1;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = part;
+    if (!LAST) {
+        tile[0][ty][tx] = v0;
+        tile[1][ty][tx] = v1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = s_red[0];
+#pragma unroll
+        for (int w = 1; w < 16; ++w) t += s_red[w];
+        A.partials[blockIdx.x + gridDim.x * blockIdx.y] = t;
+    }
+    if (LAST) return;
+    const int it = blockIdx.x * 32 + ty, jt = blockIdx.y * 32 + tx;
+    if (it < K.nx && jt < K.ny) {
+        const long long t_idx = (long long)it * K.ldT + jt + 2;
+        A.XT0[t_idx] = tile[0][tx][ty];
+        if (two) A.XT1[t_idx] = tile[1][tx][ty];
+    }
+}
+
 // One block: fixed-order FP64 sum of the back-projection's block partials,
 // then the continuation decision (STEP) or the finite check (INIT); reads
 // the scalar record `in`, writes the next one to `out`.
-template <int MODE>
+// WAVE (2D): the one-wave fixed order that the fused decisions of the
+// x-update and forward-projection kernels use, so a decision gives the same
+// bits wherever it is taken.
+template <int MODE, bool WAVE>
 __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, long long nblocks,
                                                        const DevScalars *in, DevScalars *out, ContArgs C)
 {
@@ -419,17 +510,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, l
         if (tid == 0) *out = s;
         return;
     }
-    const double total = fixed_sum_256(partials, nblocks, tid, s_w);
+    const double total = WAVE ? fixed_sum_wave(partials, nblocks, tid & 63) : fixed_sum_256(partials, nblocks, tid, s_w);
     if (tid == 0) *out = continuation_update(s, C, total, MODE == BP_INIT, true);
 }
 
-hipError_t bp_dispatch(const BPArgs &a, int mode, dim3 grd, hipStream_t st)
+hipError_t bp_dispatch(const lalm_plan *p, const BPArgs &a, int mode, dim3 grd, hipStream_t st)
 {
     dim3 blk(32, 8);
-    if (mode == BP_PLAIN) hipLaunchKernelGGL((bp_kernel<BP_PLAIN>), grd, blk, 0, st, a);
-    else if (mode == BP_INIT) hipLaunchKernelGGL((bp_kernel<BP_INIT>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((bp_kernel<BP_STEP>), grd, blk, 0, st, a);
-    return hipGetLastError();
+    if (mode == BP_PLAIN) return klaunch(p, bp_kernel<BP_PLAIN>, grd, blk, st, a);
+    if (mode == BP_INIT) return klaunch(p, bp_kernel<BP_INIT>, grd, blk, st, a);
+    return klaunch(p, bp_kernel<BP_STEP>, grd, blk, st, a);
 }
 
 template <bool IS3D>
@@ -465,36 +555,84 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
     if (!p->is3d) {
         const int nxt = ((p->nx + 63) / 64) * ((p->ny + BP2_TR - 1) / BP2_TR);
         const int nyt = ((p->nx + BP2_TR - 1) / BP2_TR) * ((p->ny + 63) / 64);
-        hipLaunchKernelGGL(bp2d_lines_kernel, dim3(nxt + nyt), dim3(64, BP2_VG), 0, st, a, nxt);
+        const hipError_t el = klaunch(p, bp2d_lines_kernel, dim3(nxt + nyt), dim3(64, BP2_VG), st, a, nxt);
+        if (el != hipSuccess || mode == BP_LINES) return el;
+        if (mode == BP_STEP) return launch_step2d(p, e.x, e.x, nullptr, nullptr, nullptr, e, nullptr, 0, true, st);
         dim3 ge((p->nx + 31) / 32, (p->ny + 7) / 8);
         a.nblocks = (int)(ge.x * ge.y);
         if (mode == BP_PLAIN) hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_PLAIN>), ge, dim3(32, 8), 0, st, a);
-        else if (mode == BP_INIT) hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_INIT>), ge, dim3(32, 8), 0, st, a);
-        else hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_STEP>), ge, dim3(32, 8), 0, st, a);
+        else hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_INIT>), ge, dim3(32, 8), 0, st, a);
     } else {
+        if (mode == BP_LINES) return hipErrorInvalidValue;
         const int kz = KZ3;
         dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + kz - 1) / kz);
         a.nblocks = (int)(grd.x * grd.y * grd.z);
-        hipError_t e = bp_dispatch(a, mode, grd, st);
+        hipError_t e = bp_dispatch(p, a, mode, grd, st);
         if (e != hipSuccess) return e;
     }
     if (mode == BP_PLAIN) return hipGetLastError();
     p->bp_nblocks = a.nblocks;
     if (mode == BP_INIT) {
         // finite check of the initial gradient: scalars advance to the other record
-        hipLaunchKernelGGL((finalize_kernel<BP_INIT>), dim3(1), dim3(256), 0, st, (const double *)p->d_partials,
-                           p->bp_nblocks, (const DevScalars *)cur_sc(p), p->d_sc + (p->sc_cur ^ 1), e.cont);
+        if (p->is3d)
+            hipLaunchKernelGGL((finalize_kernel<BP_INIT, false>), dim3(1), dim3(256), 0, st,
+                               (const double *)p->d_partials, p->bp_nblocks, (const DevScalars *)cur_sc(p),
+                               p->d_sc + (p->sc_cur ^ 1), e.cont);
+        else
+            hipLaunchKernelGGL((finalize_kernel<BP_INIT, true>), dim3(1), dim3(256), 0, st,
+                               (const double *)p->d_partials, p->bp_nblocks, (const DevScalars *)cur_sc(p),
+                               p->d_sc + (p->sc_cur ^ 1), e.cont);
         p->sc_cur ^= 1;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_step2d(const lalm_plan *p, const float *xs0, const float *xs1, float *xw, float *xo0,
+                         float *xo1, const BpEpi &e, const float *denom, int nonneg, bool last, hipStream_t st)
+{
+    if (p->is3d) return hipErrorInvalidValue;
+    if (!last && (!xo0 || !xo1 || !denom || !p->d_xt1 || !p->d_xn1)) return hipErrorInvalidValue;
+    Step2dArgs a;
+    a.k = p->k;
+    a.part = p->d_part;
+    a.part2 = p->d_part2;
+    a.G = e.G;
+    a.g = e.g;
+    a.xs0 = xs0;
+    a.xs1 = xs1;
+    a.xw = xw;
+    a.denom = denom;
+    a.gradR = p->d_gradR;
+    a.xo0 = xo0;
+    a.xo1 = xo1;
+    a.XT0 = p->d_xt;
+    a.XN0 = p->d_xn;
+    a.XT1 = p->d_xt1;
+    a.XN1 = p->d_xn1;
+    a.sc = cur_sc(p);
+    a.partials = p->d_partials;
+    a.scale = e.scale;
+    a.beta = e.beta;
+    a.inv_delta2 = e.inv_delta2;
+    a.rho_min = e.cont.rho_min;
+    a.continuation = e.cont.continuation;
+    a.nonneg = nonneg;
+    const dim3 grd((p->nx + 31) / 32, (p->ny + 31) / 32);
+    p->bp_nblocks = (long long)grd.x * grd.y;
+    return last ? klaunch(p, step2d_kernel<true>, grd, dim3(32, 32), st, a)
+                : klaunch(p, step2d_kernel<false>, grd, dim3(32, 32), st, a);
+}
+
 hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st)
 {
-    hipLaunchKernelGGL((finalize_kernel<BP_STEP>), dim3(1), dim3(256), 0, st, (const double *)p->d_partials,
-                       p->bp_nblocks, (const DevScalars *)cur_sc(p), p->d_sc + (p->sc_cur ^ 1), c);
+    const double *part = p->d_partials;
+    const DevScalars *in = cur_sc(p);
+    DevScalars *out = p->d_sc + (p->sc_cur ^ 1);
+    const hipError_t e = p->is3d
+        ? klaunch(p, finalize_kernel<BP_STEP, false>, dim3(1), dim3(256), st, part, p->bp_nblocks, in, out, c)
+        : klaunch(p, finalize_kernel<BP_STEP, true>, dim3(1), dim3(256), st, part, p->bp_nblocks, in, out, c);
     p->sc_cur ^= 1;
-    return hipGetLastError();
+    return e;
 }
 
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,

@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 OS-LALM library (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -51,7 +52,8 @@ struct DevScalars {
     long long l;      // continuation counter
     long long step;   // global subset-step counter
     int status;       // 0 ok, 1 non-finite restart indicator met
-    int pad;
+    int sel;          // 2D fused steps: x-update candidate the last decision
+                      // selected (0: restart or fixed rho, 1: continue)
     double alpha;     // Barzilai-Borwein scale of D_L (1 without it)
 };
 
@@ -92,8 +94,18 @@ struct ContArgs {
 __device__ inline double fixed_sum_256(const double *v, long long n, int tid, double *s_w)
 {
     double a = 0.0;
-    if (tid < 256)
-        for (long long t = tid; t < n; t += 256) a += v[t];
+    if (tid < 256) {
+        long long t = tid;
+        // loads in batches (one memory round trip each), additions in order
+        for (; t + 7 * 256 < n; t += 8 * 256) {
+            double u[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = v[t + k * 256];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a += u[k];
+        }
+        for (; t < n; t += 256) a += v[t];
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (tid < 256 && (tid & 63) == 0) s_w[tid >> 6] = a;
@@ -101,6 +113,37 @@ __device__ inline double fixed_sum_256(const double *v, long long n, int tid, do
     const double r = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
     __syncthreads();
     return r;
+}
+
+// Fixed-order FP64 sum of v[0..n) within one wave: lane t adds v[t],
+// v[t+64], ... in turn, then an xor butterfly over the lanes.  Floating-point
+// addition is commutative, so every lane of every wave that calls it holds
+// the same bits: the waves of many blocks can each take the same decision
+// from it without a barrier.  lane = lane index in the wave64.
+__device__ inline double fixed_sum_wave(const double *v, long long n, int lane)
+{
+    double a = 0.0;
+    long long t = lane;
+    // loads in batches (one memory round trip each), additions in order
+    for (; t + 7 * 64 < n; t += 8 * 64) {
+        double u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = v[t + k * 64];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a += u[k];
+    }
+    if (t + 3 * 64 < n) {
+        double u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = v[t + k * 64];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a += u[k];
+        t += 4 * 64;
+    }
+    for (; t < n; t += 64) a += v[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return a;
 }
 
 // d psi / dt for the hyperbola potential: t / sqrt(1 + (t/delta)^2)
@@ -139,6 +182,40 @@ __device__ inline float reg_grad_at(const GeoK &K, const float *x, int i, int j,
     return beta * s;
 }
 
+// Number-weighted neighbour sum 2 * sum_{k in N(j)} kappa_jk for voxel (i,j,k)
+// (the separable majorizer curvature of the hyperbola regularizer over beta).
+__device__ inline float reg_curv_sum(const GeoK &K, int i, int j, int k)
+{
+    const float r2 = 0.70710678118654752f, r3 = 0.57735026918962576f;
+    int cx = (i > 0) + (i < K.nx - 1);
+    int cy = (j > 0) + (j < K.ny - 1);
+    int cz = K.is3d ? (k > 0) + (k < K.nz - 1) : 0;
+    // neighbours along 1, 2 or 3 axes: counts are products of per-axis counts
+    float s1 = (float)(cx + cy + cz);
+    float s2 = (float)(cx * cy + cx * cz + cy * cz);
+    float s3 = (float)(cx * cy * cz);
+    return 2.0f * (s1 + s2 * r2 + s3 * r3);
+}
+
+// The n = 1 x-update of a step (one projected gradient step on the inner
+// problem, Sec. IV-A): s = rho G + (1 - rho) g, then
+// x+ = max(0, x - (s + grad R(x)) / (rho alpha D_L + beta C)) where
+// beta C = curv_b is the regularizer's separable curvature; a pixel with a
+// zero denominator keeps its value.  Every kernel that updates x calls this,
+// so all paths give the same bits.
+__device__ inline float x_update(float x, float G, float g, float gR, float rho, float alpha, float dl,
+                                 float curv_b, int nonneg)
+{
+    const float num = fmaf(rho, G, (1.0f - rho) * g) + gR;
+    const float den = fmaf(rho * alpha, dl, curv_b);
+    float v = x;
+    if (den > 0.0f) {
+        v = v - num / den;
+        if (nonneg) v = fmaxf(v, 0.0f);
+    }
+    return v;
+}
+
 // rho_l of the downward continuation (eq. rho_l_formula_qp): 1 at l = 0,
 // else (pi/(l+1)) sqrt(1 - (pi/(2(l+1)))^2), never below rho_min.
 __device__ inline double continuation_rho(long long l, double rho_min)
@@ -171,6 +248,7 @@ __device__ inline DevScalars continuation_update(const DevScalars &in, const Con
         o.l = restart ? 0 : in.l + 1;
         o.rho = continuation_rho(o.l, C.rho_min);
     }
+    if (!o.status) o.sel = (C.continuation && o.l != 0) ? 1 : 0;
     o.xi = xi;
     if (record && jstep < C.st_cap) {
         if (C.st_rho) C.st_rho[jstep] = in.rho;
@@ -210,6 +288,10 @@ struct lalm_plan {
     float *d_part2 = nullptr;           // 2D: back-projection of the y-dominant rays
     float *d_v = nullptr;               // inner FISTA iterate (n_inner > 1); part, part2 hold z
     float *d_fbpq = nullptr;            // 2D: filtered sinogram of the FBP
+    // 2D fused steps: the second set of projector layouts and the x-update
+    // candidates of two consecutive steps ([2 steps][2 candidates][image])
+    float *d_xt1 = nullptr, *d_xn1 = nullptr;
+    float *d_xc = nullptr;
     double *d_partials = nullptr;       // reduction partials
     int64_t n_partials = 0;
     // two device scalar records: each continuation decision reads one and
@@ -223,17 +305,35 @@ struct lalm_plan {
     double *d_tmp = nullptr;            // small FP64 scratch (monitors)
     int fp_nseg = 1;
     // optional per-kernel event timing
+    // (each timed kernel carries its own start / stop events on its dispatch;
+    // a class is the set of kernels of one part of a step)
     bool prof = false;
-    std::vector<hipEvent_t> prof_ev;     // pool: pairs (start, stop)
-    std::vector<int> prof_kind;          // kernel class of each recorded pair
-    size_t prof_used = 0;
+    mutable std::vector<hipEvent_t> prof_ev;   // pool: pairs (start, stop)
+    mutable std::vector<int> prof_kind;        // class of each recorded pair
+    mutable size_t prof_used = 0;
+    mutable int prof_cls = -1;                 // class being recorded, -1: none
     double prof_ms[3] = {0, 0, 0};
-    int64_t prof_n[3] = {0, 0, 0};
+    int64_t prof_n[3] = {0, 0, 0};             // class instances (steps)
 };
 
 namespace lalm {
 
 void set_error(const std::string &msg);
+
+// With profiling on and a class open: a (start, stop) event pair for one
+// kernel launch, attributed to that class.
+bool prof_pair(const lalm_plan *p, hipEvent_t *start, hipEvent_t *stop);
+
+// Kernel launch that, while profiling, times the kernel by the events of
+// its own dispatch (no extra packets in the stream between kernels).
+template <typename K, typename... Args>
+inline hipError_t klaunch(const lalm_plan *p, K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof_pair(p, &e0, &e1)) hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    return hipGetLastError();
+}
 
 // Launchers (defined in the .hip files).  All return hipError_t of the launch.
 // Forward projection of the subset starting at slot `slot0` holding `nview`
@@ -244,8 +344,16 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
                      int64_t *n_blocks_out, int check_status, hipStream_t st);
 
 inline lalm::DevScalars *cur_sc(const lalm_plan *p) { return p->d_sc + p->sc_cur; }
+// The same forward projection, first taking the continuation decision of
+// the previous step (every wave reduces the fused step kernel's partials in
+// the same fixed order; one thread records it in the other scalar record)
+// and reading the projector layouts of the candidate it selects.
+hipError_t launch_fp_decide(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
+                            float *out, const ContArgs &cont, hipStream_t st);
 
-enum BpMode { BP_PLAIN = 0, BP_INIT = 1, BP_STEP = 2 };
+// BP_LINES (2D): the partial back-projections of a STEP only; the fused
+// step kernel (launch_step2d) follows.
+enum BpMode { BP_PLAIN = 0, BP_INIT = 1, BP_STEP = 2, BP_LINES = 3 };
 struct BpEpi {
     float scale;           // PLAIN: scale; INIT/STEP: M
     int accumulate;        // PLAIN
@@ -262,6 +370,17 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
                      const BpEpi &e, hipStream_t st);
 // Standalone continuation decision after the last BP_STEP of a call.
 hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st);
+// 2D only: the two partial back-projections of a step, pointwise, fused
+// with the next step's x-update.  x of this step is xs[sel] of the current
+// scalar record (xs0 == xs1 when it is not a candidate); xw, when set,
+// receives a copy of it.  G+, the g-update and the restart-indicator
+// partials as BP_STEP; then, unless last, the next x for both values rho
+// can take after the pending decision (restart: rho_0 = 1; continue:
+// rho_{l+1}; one value with a fixed rho) into xo0 / xo1 and the two layout
+// sets.  last: instead grad R(x) into the plan's gradient image.
+hipError_t launch_step2d(const lalm_plan *p, const float *xs0, const float *xs1, float *xw, float *xo0,
+                         float *xo1, const BpEpi &e, const float *denom, int nonneg, bool last,
+                         hipStream_t st);
 
 enum UpdMode { UPD_LAYOUT = 0, UPD_ONES = 1, UPD_STEP = 2 };
 // UPD_STEP with cont != null first makes the pending continuation decision

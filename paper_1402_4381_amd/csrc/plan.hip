@@ -65,6 +65,23 @@ hipError_t dev_alloc(T **p, size_t n)
 
 void lalm::set_error(const std::string &msg) { g_err = msg; }
 
+bool lalm::prof_pair(const lalm_plan *p, hipEvent_t *start, hipEvent_t *stop)
+{
+    if (!p->prof || p->prof_cls < 0) return false;
+    if (p->prof_used + 2 > p->prof_ev.size()) {
+        const size_t n = p->prof_ev.size();
+        p->prof_ev.resize(std::max<size_t>(64, 2 * n));
+        for (size_t i = n; i < p->prof_ev.size(); ++i)
+            if (hipEventCreate(&p->prof_ev[i]) != hipSuccess) p->prof_ev[i] = nullptr;
+    }
+    *start = p->prof_ev[p->prof_used];
+    *stop = p->prof_ev[p->prof_used + 1];
+    if (!*start || !*stop) return false;
+    p->prof_used += 2;
+    p->prof_kind.push_back(p->prof_cls);
+    return true;
+}
+
 extern "C" const char *lalm_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *lalm_version(void) { return "lalm-gfx950 0.1"; }
@@ -88,6 +105,9 @@ static void free_plan(lalm_plan *p)
     (void)hipFree(p->d_gradR);
     (void)hipFree(p->d_v);
     (void)hipFree(p->d_fbpq);
+    (void)hipFree(p->d_xt1);
+    (void)hipFree(p->d_xn1);
+    (void)hipFree(p->d_xc);
     (void)hipFree(p->d_r);
     (void)hipFree(p->d_part);
     (void)hipFree(p->d_part2);
@@ -292,7 +312,12 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(dev_alloc(&p->d_part, nvox));
     chk(dev_alloc(&p->d_part2, nvox));
     chk(dev_alloc(&p->d_v, nvox));
-    if (!is3d) chk(dev_alloc(&p->d_fbpq, (size_t)p->nv * p->nb));
+    if (!is3d) {
+        chk(dev_alloc(&p->d_fbpq, (size_t)p->nv * p->nb));
+        chk(dev_alloc(&p->d_xt1, (size_t)g.nx * K.slabT));
+        chk(dev_alloc(&p->d_xn1, (size_t)g.ny * K.slabN));
+        chk(dev_alloc(&p->d_xc, 4 * nvox));
+    }
     chk(dev_alloc(&p->d_partials, (size_t)p->n_partials));
     chk(dev_alloc(&p->d_sc, 2));
     chk(dev_alloc(&p->d_tmp, (size_t)(64 + M)));
@@ -309,6 +334,10 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(hipMemcpy(p->d_rowf, rowf.data(), nr * sizeof(float), hipMemcpyHostToDevice));
     chk(hipMemset(p->d_xt, 0, (size_t)g.nx * K.slabT * sizeof(float)));
     chk(hipMemset(p->d_xn, 0, (size_t)g.ny * K.slabN * sizeof(float)));
+    if (!is3d) {
+        chk(hipMemset(p->d_xt1, 0, (size_t)g.nx * K.slabT * sizeof(float)));
+        chk(hipMemset(p->d_xn1, 0, (size_t)g.ny * K.slabN * sizeof(float)));
+    }
     chk(hipMemset(p->d_gradR, 0, nvox * sizeof(float)));
     chk(hipMemset(p->d_sc, 0, 2 * sizeof(lalm::DevScalars)));
     chk(hipDeviceSynchronize());

@@ -28,31 +28,66 @@ struct FPArgs {
     float *out;
     double *partials;       // mode 1
     const int *status;      // skip when set (LALM steps only)
+    // DEC: the pending continuation decision, then the selected layouts
+    const float *XT1, *XN1;
+    const DevScalars *sc_in;
+    DevScalars *sc_out;
+    const double *dec_part;
+    long long dec_n;
+    ContArgs cont;
 };
 
-template <bool IS3D, int NSEG, int MODE>
+template <bool IS3D, int NSEG, int MODE, bool DEC>
 __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 {
     const GeoK &K = A.k;
     const int lane = threadIdx.x, seg = threadIdx.y;
-    if (A.status && *A.status) return;
     const long long q = (long long)blockIdx.x * 64 + lane;
     const bool valid = q < A.nrays;
     float acc = 0.0f;
     RayRec rr{0.f, 0.f, 0.f, 1u};
-    int r = 0;
+    int r = 0, kv = 0, b = 0;
+    float yv = 0.0f, wv = 1.0f;
+    // loads that do not depend on the image go out first
     if (valid) {
-        const int b = (int)(q % K.nb);
+        b = (int)(q % K.nb);
         const long long vrow = q / K.nb;
         r = IS3D ? (int)(vrow % K.nr) : 0;
-        const int kv = IS3D ? (int)(vrow / K.nr) : (int)vrow;
+        kv = IS3D ? (int)(vrow / K.nr) : (int)vrow;
         rr = A.rays[(long long)kv * K.nb + b];
+        if (seg == 0) {
+            if (A.y) yv = A.y[q];
+            if (A.w) wv = A.w[q];
+        }
+    }
+    const float *XT = A.XT, *XN = A.XN;
+    if (DEC) {
+        // every wave reduces the same partials in the same order, so all
+        // take the same decision; one thread records it
+        const double xi = fixed_sum_wave(A.dec_part, A.dec_n, lane);
+        const DevScalars s0 = *A.sc_in;
+        const bool lead = blockIdx.x == 0 && lane == 0 && seg == 0;
+        if (s0.status) {
+            if (lead) *A.sc_out = s0;
+            return;
+        }
+        const DevScalars s1 = continuation_update(s0, A.cont, xi, false, lead);
+        if (lead) *A.sc_out = s1;
+        if (s1.status) return;
+        if (s1.sel) {
+            XT = A.XT1;
+            XN = A.XN1;
+        }
+    } else if (A.status && *A.status) {
+        return;
+    }
+    if (valid) {
         const bool ydom = meta_ydom(rr.meta);
         const int ns = ydom ? K.ny : K.nx;
         const int seglen = (ns + NSEG - 1) / NSEG;
         int s0 = max(meta_lo(rr.meta), seg * seglen);
         int s1 = min(meta_hi(rr.meta), seg * seglen + seglen - 1);
-        const float *img = ydom ? A.XN : A.XT;
+        const float *img = ydom ? XN : XT;
         const int lim = ydom ? K.nx : K.ny;
         if (!IS3D) {
             const int ld = ydom ? K.ldN : K.ldT;
@@ -151,11 +186,9 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 #pragma unroll
         for (int t = 1; t < NSEG; ++t) acc += red[t][lane];
     }
-    float val = 0.0f, wv = 0.0f;
+    float val = 0.0f;
     if (valid) {
         const float proj = acc * rr.sc * (IS3D ? A.rowf[r] : 1.0f);
-        const float yv = A.y ? A.y[q] : 0.0f;
-        wv = A.w ? A.w[q] : 1.0f;
         val = proj - yv;
         if (MODE == 0) A.out[q] = wv * val;
     }
@@ -168,22 +201,24 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 }
 
 template <bool IS3D, int NSEG>
-hipError_t fp_dispatch_mode(const FPArgs &a, int mode, long long nblk, hipStream_t st)
+hipError_t fp_dispatch_mode(const lalm_plan *p, const FPArgs &a, int mode, long long nblk, hipStream_t st)
 {
     dim3 blk(64, NSEG), grd((unsigned)nblk);
-    if (mode == 0) hipLaunchKernelGGL((fp_kernel<IS3D, NSEG, 0>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((fp_kernel<IS3D, NSEG, 1>), grd, blk, 0, st, a);
-    return hipGetLastError();
+    // mode 2: mode 0 after the pending continuation decision (2D)
+    if (mode == 0) return klaunch(p, fp_kernel<IS3D, NSEG, 0, false>, grd, blk, st, a);
+    if (mode == 1) return klaunch(p, fp_kernel<IS3D, NSEG, 1, false>, grd, blk, st, a);
+    if (!IS3D) return klaunch(p, fp_kernel<false, NSEG, 0, true>, grd, blk, st, a);
+    return hipErrorInvalidValue;
 }
 
 template <bool IS3D>
-hipError_t fp_dispatch(const FPArgs &a, int nseg, int mode, long long nblk, hipStream_t st)
+hipError_t fp_dispatch(const lalm_plan *p, const FPArgs &a, int nseg, int mode, long long nblk, hipStream_t st)
 {
     switch (nseg) {
-    case 1: return fp_dispatch_mode<IS3D, 1>(a, mode, nblk, st);
-    case 2: return fp_dispatch_mode<IS3D, 2>(a, mode, nblk, st);
-    case 4: return fp_dispatch_mode<IS3D, 4>(a, mode, nblk, st);
-    default: return fp_dispatch_mode<IS3D, 8>(a, mode, nblk, st);
+    case 1: return fp_dispatch_mode<IS3D, 1>(p, a, mode, nblk, st);
+    case 2: return fp_dispatch_mode<IS3D, 2>(p, a, mode, nblk, st);
+    case 4: return fp_dispatch_mode<IS3D, 4>(p, a, mode, nblk, st);
+    default: return fp_dispatch_mode<IS3D, 8>(p, a, mode, nblk, st);
     }
 }
 
@@ -209,21 +244,6 @@ struct UpdArgs {
     // first of several inner iterations: v and the next momentum point go here
     float *vout, *zout;
 };
-
-// Number-weighted neighbour sum 2 * sum_{k in N(j)} kappa_jk for voxel (i,j,k)
-// (the separable majorizer curvature of the hyperbola regularizer over beta).
-__device__ inline float reg_curv_sum(const GeoK &K, int i, int j, int k)
-{
-    const float r2 = 0.70710678118654752f, r3 = 0.57735026918962576f;
-    int cx = (i > 0) + (i < K.nx - 1);
-    int cy = (j > 0) + (j < K.ny - 1);
-    int cz = K.is3d ? (k > 0) + (k < K.nz - 1) : 0;
-    // neighbours along 1, 2 or 3 axes: counts are products of per-axis counts
-    float s1 = (float)(cx + cy + cz);
-    float s2 = (float)(cx * cy + cx * cz + cy * cz);
-    float s3 = (float)(cx * cy * cz);
-    return 2.0f * (s1 + s2 * r2 + s3 * r3);
-}
 
 template <bool IS3D, int MODE>
 __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
@@ -251,14 +271,13 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         }
     }
     if (MODE == UPD_STEP) {
-        __shared__ double s_w[4];
         DevScalars s = *A.sc;
         if (A.do_finalize) {
-            // every block takes the same decision from the same fixed-order
-            // sum; the first block records it in the other scalar record
+            // every wave takes the same decision from the same fixed-order
+            // sum; the first thread records it in the other scalar record
             const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tx == 0 && ty == 0;
             if (!s.status) {
-                const double xi = fixed_sum_256(A.partials, A.nblocks, tx + 32 * ty, s_w);
+                const double xi = fixed_sum_wave(A.partials, A.nblocks, (tx + 32 * ty) & 63);
                 s = continuation_update(s, A.cont, xi, false, lead);
             }
             if (lead) *A.sc_out = s;
@@ -266,12 +285,7 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         if (s.status) return;
         const float rho = (float)s.rho;
         if (inside) {
-            const float num = fmaf(rho, Gv, (1.0f - rho) * gv) + rv;
-            const float den = fmaf(rho * (float)s.alpha, dv, A.beta * reg_curv_sum(K, i, j, k));
-            if (den > 0.0f) {
-                v = v - num / den;
-                if (A.nonneg) v = fmaxf(v, 0.0f);
-            }
+            v = x_update(v, Gv, gv, rv, rho, (float)s.alpha, dv, A.beta * reg_curv_sum(K, i, j, k), A.nonneg);
             if (A.vout) {
                 A.vout[idx] = v;                  // first FISTA momentum is zero: z = v
                 A.zout[idx] = v;
@@ -363,13 +377,12 @@ __global__ void __launch_bounds__(1024) inner_kernel(InnerArgs A)
 }
 
 template <bool IS3D>
-hipError_t upd_dispatch(const UpdArgs &a, int mode, hipStream_t st)
+hipError_t upd_dispatch(const lalm_plan *p, const UpdArgs &a, int mode, hipStream_t st)
 {
     dim3 blk(32, 32), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, a.k.nz);
-    if (mode == UPD_LAYOUT) hipLaunchKernelGGL((update_kernel<IS3D, UPD_LAYOUT>), grd, blk, 0, st, a);
-    else if (mode == UPD_ONES) hipLaunchKernelGGL((update_kernel<IS3D, UPD_ONES>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((update_kernel<IS3D, UPD_STEP>), grd, blk, 0, st, a);
-    return hipGetLastError();
+    if (mode == UPD_LAYOUT) return klaunch(p, update_kernel<IS3D, UPD_LAYOUT>, grd, blk, st, a);
+    if (mode == UPD_ONES) return klaunch(p, update_kernel<IS3D, UPD_ONES>, grd, blk, st, a);
+    return klaunch(p, update_kernel<IS3D, UPD_STEP>, grd, blk, st, a);
 }
 
 __global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long long step, double alpha)
@@ -380,7 +393,7 @@ __global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long
         sc->l = l;
         sc->step = step;
         sc->status = 0;
-        sc->pad = 0;
+        sc->sel = 0;
         sc->alpha = alpha;
     }
 }
@@ -457,11 +470,50 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.out = out;
     a.partials = p->d_partials + part_off;
     a.status = check_status ? &cur_sc(p)->status : nullptr;
+    a.XT1 = a.XN1 = nullptr;
+    a.sc_in = nullptr;
+    a.sc_out = nullptr;
+    a.dec_part = nullptr;
+    a.dec_n = 0;
+    a.cont = ContArgs{};
     long long nblk = (a.nrays + 63) / 64;
     if (n_blocks_out) *n_blocks_out = nblk;
     if (nblk == 0) return hipSuccess;
-    return p->is3d ? fp_dispatch<true>(a, p->fp_nseg, mode, nblk, st)
-                   : fp_dispatch<false>(a, p->fp_nseg, mode, nblk, st);
+    return p->is3d ? fp_dispatch<true>(p, a, p->fp_nseg, mode, nblk, st)
+                   : fp_dispatch<false>(p, a, p->fp_nseg, mode, nblk, st);
+}
+
+hipError_t launch_fp_decide(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
+                            float *out, const ContArgs &cont, hipStream_t st)
+{
+    if (p->is3d || !p->d_xt1 || !p->d_xn1) return hipErrorInvalidValue;
+    FPArgs a;
+    a.k = p->k;
+    a.rays = p->d_rays + slot0 * p->nb;
+    a.raysz = nullptr;
+    a.views = p->d_views + slot0;
+    a.rowv = p->d_rowv;
+    a.rowf = p->d_rowf;
+    a.XT = p->d_xt;
+    a.XN = p->d_xn;
+    a.XT1 = p->d_xt1;
+    a.XN1 = p->d_xn1;
+    a.nrays = (long long)nview * p->rays_per_view;
+    a.y = y;
+    a.w = w;
+    a.out = out;
+    a.partials = nullptr;
+    a.status = nullptr;
+    a.sc_in = cur_sc(p);
+    a.sc_out = p->d_sc + (p->sc_cur ^ 1);
+    a.dec_part = p->d_partials;
+    a.dec_n = p->bp_nblocks;
+    a.cont = cont;
+    const long long nblk = (a.nrays + 63) / 64;
+    if (nblk == 0) return hipErrorInvalidValue;     // every subset holds a view
+    const hipError_t e = fp_dispatch<false>(p, a, p->fp_nseg, 2, nblk, st);
+    p->sc_cur ^= 1;
+    return e;
 }
 
 hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G, const float *g,
@@ -488,7 +540,7 @@ hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G,
     else a.cont = ContArgs{};
     a.vout = mode == UPD_STEP ? vout : nullptr;
     a.zout = mode == UPD_STEP ? zout : nullptr;
-    hipError_t e = p->is3d ? upd_dispatch<true>(a, mode, st) : upd_dispatch<false>(a, mode, st);
+    hipError_t e = p->is3d ? upd_dispatch<true>(p, a, mode, st) : upd_dispatch<false>(p, a, mode, st);
     if (a.do_finalize) p->sc_cur ^= 1;
     return e;
 }
@@ -514,14 +566,10 @@ hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zou
     a.mom = mom;
     a.nonneg = nonneg;
     dim3 blk(32, 32), grd((p->nx + 31) / 32, (p->ny + 31) / 32, p->nz);
-    if (p->is3d) {
-        if (last) hipLaunchKernelGGL((inner_kernel<true, true>), grd, blk, 0, st, a);
-        else hipLaunchKernelGGL((inner_kernel<true, false>), grd, blk, 0, st, a);
-    } else {
-        if (last) hipLaunchKernelGGL((inner_kernel<false, true>), grd, blk, 0, st, a);
-        else hipLaunchKernelGGL((inner_kernel<false, false>), grd, blk, 0, st, a);
-    }
-    return hipGetLastError();
+    if (p->is3d) return last ? klaunch(p, inner_kernel<true, true>, grd, blk, st, a)
+                             : klaunch(p, inner_kernel<true, false>, grd, blk, st, a);
+    return last ? klaunch(p, inner_kernel<false, true>, grd, blk, st, a)
+                : klaunch(p, inner_kernel<false, false>, grd, blk, st, a);
 }
 
 hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step, double alpha,

@@ -437,6 +437,45 @@ def test_determinism_and_checkpoint_resume(L):
     assert a.rho == saved.rho and a.l == saved.l
 
 
+@pytest.mark.parametrize("mode", ["continuation", "fixed", "forced"])
+def test_fused_steps_equal_single_steps(L, mode):
+    """Within one call of several 2D steps the step kernel also computes the
+    next x for both values the pending decision can give rho, and the next
+    forward projection picks one; single-step calls take no such shortcut.
+    Both are the same arithmetic: x, g, G, rho, l and the recorded restart
+    indicators are bit-identical, with the continuation, a fixed rho and a
+    forced restart pattern."""
+    cfg = synth.get_config("fan2d_128")
+    data = _problem(cfg)
+    M, n = 4, 36
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    kw = dict(continuation=mode != "fixed", rho_fixed=0.1)
+    if mode == "forced":
+        pat = np.zeros(n, dtype=np.uint8)
+        pat[[3, 4, 11, 20, 21, 22, 30]] = 1
+        kw["forced_restart"] = gpu(pat, torch.uint8)
+
+    def stats():
+        return dict(rho=torch.zeros(n, dtype=torch.float64, device=DEV),
+                    xi=torch.zeros(n, dtype=torch.float64, device=DEV),
+                    restart=torch.zeros(n, dtype=torch.uint8, device=DEV))
+    z = torch.zeros(plan.image_elems, device=DEV)
+    a, sa = L.LalmState.zeros_like(z.clone()), stats()
+    L.lalm_iterate(plan, y, w, denom, beta, delta, a, n, stats=sa, **kw)
+    b, sb = L.LalmState.zeros_like(z.clone()), stats()
+    for _ in range(n):
+        L.lalm_iterate(plan, y, w, denom, beta, delta, b, 1, stats=sb, **kw)
+    restarts = int(sa["restart"].sum().item())
+    say("fused vs single steps (%s): %d restarts, rho %.6f, l %d" % (mode, restarts, a.rho, a.l))
+    assert torch.equal(a.x, b.x) and torch.equal(a.g, b.g) and torch.equal(a.grad, b.grad)
+    assert a.rho == b.rho and a.l == b.l and a.step == b.step == n
+    for k in ("rho", "xi", "restart"):
+        assert torch.equal(sa[k], sb[k]), k
+    if mode == "forced":
+        assert np.array_equal(sa["restart"].cpu().numpy(), pat)
+
+
 def test_nonfinite_data_is_reported_and_image_stays_finite(L):
     cfg = synth.get_config("fan2d_128")
     data = _problem(cfg)
