@@ -496,6 +496,43 @@ def test_nonfinite_data_is_reported_and_image_stays_finite(L):
     assert not torch.equal(st.x, good)
 
 
+def test_fused_steps_stop_like_single_steps(L):
+    """A non-finite restart indicator met a few steps into a call (the
+    forward projection that takes the decision finds it): the call reports
+    it and leaves x, g, G and the step count exactly as single-step calls do
+    (x is the last accepted iterate, not a speculative candidate)."""
+    cfg = synth.get_config("fan2d_128")
+    data = _problem(cfg)
+    M = 4
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    z = torch.zeros(plan.image_elems, device=DEV)
+    a = L.LalmState.zeros_like(z.clone())
+    L.lalm_iterate(plan, y, w, denom, beta, delta, a, 5)
+    b = a.clone()
+    # poison the subset projected three steps into the next call
+    ybad = y.clone()
+    s = plan.subset_slice(int(plan.order[(a.step + 3) % M]))
+    ybad[s.start + 50] = float("nan")
+    with pytest.raises(L.LalmError) as ea:
+        L.lalm_iterate(plan, ybad, w, denom, beta, delta, a, 8)
+    assert ea.value.status == L.LALM_E_NONFINITE
+    for _ in range(8):
+        try:
+            L.lalm_iterate(plan, ybad, w, denom, beta, delta, b, 1)
+        except L.LalmError as eb:
+            assert eb.status == L.LALM_E_NONFINITE
+            break
+    else:
+        raise AssertionError("single steps did not meet the non-finite indicator")
+    say("stopped at step %d (fused call) / %d (single steps)" % (a.step, b.step))
+    assert a.step == b.step
+    assert torch.isfinite(a.x).all()
+    assert torch.equal(a.x, b.x)
+    assert torch.equal(torch.nan_to_num(a.g, nan=7.0), torch.nan_to_num(b.g, nan=7.0))
+    assert torch.equal(torch.nan_to_num(a.grad, nan=7.0), torch.nan_to_num(b.grad, nan=7.0))
+
+
 def test_edge_cases(L):
     # every subset a single view; one subset; zero steps
     cfg = synth.get_config("tiny2d")
