@@ -32,7 +32,7 @@ import numpy as np
 
 
 def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=600, xstar_iters=6000,
-        seed=None, inners=(2, 5), dev="cuda:0", xstar_inner=None, bb=True):
+        seed=None, inners=(2, 5), dev="cuda:0", xstar_inner=None, bb=True, beta_scale=1.0):
     import torch
     import synth
     from paper_1402_4381_amd import lalm
@@ -40,7 +40,7 @@ def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=6
     M = cfg["M"]
     data = synth.make_problem_data(cfg, seed)
     geom = synth.geometry_of(cfg)
-    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    beta, delta = cfg["beta"] * beta_scale, synth.configs.delta_mu(cfg)
     radius, hu = synth.roi_radius(cfg), synth.HU_PER_MU
     r64 = torch.zeros(1, dtype=torch.float64, device=dev)
 
@@ -121,7 +121,8 @@ def run(workload="fan2d_512", rhos=(1.0, 0.2, 0.1, 0.05), iters=60, iters_rho1=6
             row["%g" % L] = None if (k1 is None or kr is None) else round(k1 / kr, 2)
         accel["rho=%g" % r] = row
     iters_to = {name: {"%g" % L: first_below(h, L) for L in levels} for name, h in curves.items()}
-    return dict(workload=workload, M=M, xstar_iters=xstar_iters, xstar_inner=xstar_inner,
+    return dict(workload=workload, M=M, beta=beta, beta_scale=beta_scale, xstar_iters=xstar_iters,
+                xstar_inner=xstar_inner,
                 xstar_last100_change_hu=round(change, 5) if xstar_inner is None else None,
                 xstar_last10_change_hu=round(change, 5) if xstar_inner is not None else None,
                 iterations_to_level=iters_to, acceleration_over_rho1=accel,
@@ -138,11 +139,12 @@ def main(argv=None):
                     help="x* from M-subset OS-LALM with this many inner FISTA iterations (volumes)")
     ap.add_argument("--inners", default="2,5", help="inner FISTA counts of the extra continuation runs")
     ap.add_argument("--no-bb", action="store_true")
+    ap.add_argument("--beta-scale", type=float, default=1.0, help="factor on the workload's beta")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     inners = tuple(int(v) for v in args.inners.split(",") if v)
     res = run(args.workload, iters=args.iters, iters_rho1=args.iters_rho1, xstar_iters=args.xstar_iters,
-              inners=inners, xstar_inner=args.xstar_inner, bb=not args.no_bb)
+              inners=inners, xstar_inner=args.xstar_inner, bb=not args.no_bb, beta_scale=args.beta_scale)
     print(json.dumps({k: v for k, v in res.items() if k != "curves"}), flush=True)
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
