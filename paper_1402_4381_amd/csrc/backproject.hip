@@ -25,6 +25,7 @@ namespace lalm {
 namespace {
 
 constexpr int KZ3 = 8;   // slices per thread in 3D
+constexpr int BP3_RW = 3;   // detector rows per slice whose gathers go out together
 
 struct BPArgs {
     GeoK k;
@@ -52,6 +53,27 @@ __device__ inline double block_sum_256(double v, double *lds)
     double t = 0.0;
     if (tid == 0) t = (lds[0] + lds[1]) + (lds[2] + lds[3]);
     return t;   // valid in thread 0
+}
+
+// atan(t) = t P(t^2) on [0, 1] with a degree-5 polynomial P fitted by
+// reweighted least squares on Chebyshev nodes (max error 1.7e-6 rad), and
+// atan(t) = pi/2 - atan(1/t) above 1.  Used only to bound channel windows;
+// the window margin covers its error.  (The 3D kernel and the 2D line
+// kernel both use it.)
+__device__ inline float atan_window(float t)
+{
+    const float at = fabsf(t);
+    const bool big = at > 1.0f;
+    const float z = big ? __frcp_rn(at) : at;
+    const float z2 = z * z;
+    float p = fmaf(z2, -0.011719409376382828f, 0.05264794081449509f);
+    p = fmaf(z2, p, -0.11642685532569885f);
+    p = fmaf(z2, p, 0.19354040920734406f);
+    p = fmaf(z2, p, -0.33262279629707336f);
+    p = fmaf(z2, p, 0.9999772310256958f);
+    float r = z * p;
+    r = big ? 1.5707963267948966f - r : r;
+    return copysignf(r, t);
 }
 
 // 3D back-projection, voxel driven (the 2D one is the line kernel below):
@@ -97,7 +119,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
             const float ddx = X - V.sx, ddy = Y - V.sy;
             const float dc = -(ddx * V.cb + ddy * V.sb);
             const float dp = ddx * V.sb - ddy * V.cb;
-            const float gam = atan2f(dp, dc);
+            const float gam = atan_window(__fdividef(dp, dc));   // dc > 0: in front of the source
             const float bc = fmaf(gam, K.dsd_over_ds, K.bin_center);
             const float dist = sqrtf(fmaf(ddx, ddx, ddy * ddy));
             const float hw = dist > 2.0f * K.dmax ? K.dmax / (dist - K.dmax) * K.dsd_over_ds + 0.05f
@@ -127,14 +149,32 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                         if (k >= K.nz) break;
                         const int r0 = max(0, (int)ceilf(fmaf((float)(k - 1) - V.z0, inv, K.row_center) - 0.01f));
                         const int r1 = min(K.nr - 1, (int)floorf(fmaf((float)(k + 1) - V.z0, inv, K.row_center) + 0.01f));
-                        for (int rw = r0; rw <= r1; ++rw) {
+                        // the first BP3_RW rows of the window: weights first, the
+                        // residual gathers issued together (clamped rows, unused
+                        // beyond r1), then accumulated in row order
+                        float wz[BP3_RW], rr[BP3_RW];
+#pragma unroll
+                        for (int u = 0; u < BP3_RW; ++u) {
+                            const int rw = min(r0 + u, K.nr - 1);
                             const float zeta = fmaf(s_rowv[rw], qz, V.z0);
                             const float zl = floorf(zeta);
                             const float h = zeta - zl;
                             const int k0 = (int)zl;
-                            const float wz = (k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f);
-                            if (wz != 0.0f)
-                                acc[t] = fmaf(base * wz * s_rowf[rw], rcol[(long long)rw * K.nb], acc[t]);
+                            wz[u] = (r0 + u > r1) ? 0.0f : ((k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f));
+                            rr[u] = rcol[rw * K.nb];
+                        }
+#pragma unroll
+                        for (int u = 0; u < BP3_RW; ++u)
+                            if (wz[u] != 0.0f)
+                                acc[t] = fmaf(base * wz[u] * s_rowf[r0 + u], rr[u], acc[t]);
+                        for (int rw = r0 + BP3_RW; rw <= r1; ++rw) {
+                            const float zeta = fmaf(s_rowv[rw], qz, V.z0);
+                            const float zl = floorf(zeta);
+                            const float h = zeta - zl;
+                            const int k0 = (int)zl;
+                            const float w1 = (k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f);
+                            if (w1 != 0.0f)
+                                acc[t] = fmaf(base * w1 * s_rowf[rw], rcol[rw * K.nb], acc[t]);
                         }
                     }
                 }
@@ -201,26 +241,6 @@ constexpr int BP2_TR = 16;     // band width of a tile
 constexpr int BP2_LD = 64;     // LDS stride between accumulator rows: a row is one bank each per lane
 constexpr int BP2_ROWS = BP2_TR + 4;   // two padding rows on each side of the band
 constexpr int BP2_WMAX = 256;  // staged rays per wave and view
-
-// atan(t) = t P(t^2) on [0, 1] with a degree-5 polynomial P fitted by
-// reweighted least squares on Chebyshev nodes (max error 1.7e-6 rad), and
-// atan(t) = pi/2 - atan(1/t) above 1.  Used only to bound channel windows;
-// the window margin covers its error.
-__device__ inline float atan_window(float t)
-{
-    const float at = fabsf(t);
-    const bool big = at > 1.0f;
-    const float z = big ? __frcp_rn(at) : at;
-    const float z2 = z * z;
-    float p = fmaf(z2, -0.011719409376382828f, 0.05264794081449509f);
-    p = fmaf(z2, p, -0.11642685532569885f);
-    p = fmaf(z2, p, 0.19354040920734406f);
-    p = fmaf(z2, p, -0.33262279629707336f);
-    p = fmaf(z2, p, 0.9999772310256958f);
-    float r = z * p;
-    r = big ? 1.5707963267948966f - r : r;
-    return copysignf(r, t);
-}
 
 // Continuous channel coordinate of the ray from the view's source through
 // the point (px, py).  The point lies in front of the source (dc > 0).
