@@ -37,6 +37,8 @@ struct FPArgs {
     ContArgs cont;
 };
 
+constexpr int FP3_U = 8;   // 3D: samples whose taps are loaded together
+
 template <bool IS3D, int NSEG, int MODE, bool DEC>
 __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 {
@@ -138,11 +140,12 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
             const int ld = ydom ? K.ldN : K.ldT;
             const long long slab = ydom ? K.slabN : K.slabT;
             const float *base = img + 2 * ld + 2;
+            // FP3_U samples per round: their tap loads go out together
             int s = s0;
-            for (; s + 1 <= s1; s += 2) {
-                float v00[2], v01[2], v10[2], v11[2], f[2], h[2];
+            for (; s + FP3_U - 1 <= s1; s += FP3_U) {
+                float v00[FP3_U], v01[FP3_U], v10[FP3_U], v11[FP3_U], f[FP3_U], h[FP3_U];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
+                for (int u = 0; u < FP3_U; ++u) {
                     const float eta = fmaf((float)(s + u), rr.c, rr.a);
                     const float qz = fmaf((float)(s + u), rz.k, rz.m);
                     const float zeta = fmaf(vr, qz, z0);
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
                     v00[u] = pp[0]; v01[u] = pp[1]; v10[u] = pp[ld]; v11[u] = pp[ld + 1];
                 }
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
+                for (int u = 0; u < FP3_U; ++u) {
                     const float lo = fmaf(f[u], v01[u] - v00[u], v00[u]);
                     const float up = fmaf(f[u], v11[u] - v10[u], v10[u]);
                     acc += fmaf(h[u], up - lo, lo);
