@@ -25,7 +25,7 @@ namespace lalm {
 namespace {
 
 constexpr int KZ3 = 8;   // slices per thread in 3D
-constexpr int BP3_RW = 3;   // detector rows per slice whose gathers go out together
+constexpr int BP3_RW = 2;   // detector rows per slice whose gathers go out together
 
 struct BPArgs {
     GeoK k;
