@@ -111,6 +111,22 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 #pragma unroll
                 for (int u = 0; u < 8; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
             }
+            if (s + 3 <= s1) {                 // four of the remaining samples together
+                float v0[4], v1[4], f[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float eta = fmaf((float)(s + u), rr.c, rr.a);
+                    const float fl = floorf(eta);
+                    f[u] = eta - fl;
+                    const int j0 = min(max((int)fl, -2), lim);
+                    const float *pp = base + (long long)(s + u) * ld + j0;
+                    v0[u] = pp[0];
+                    v1[u] = pp[1];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
+                s += 4;
+            }
             for (; s <= s1; ++s) {
                 const float eta = fmaf((float)s, rr.c, rr.a);
                 const float fl = floorf(eta);
