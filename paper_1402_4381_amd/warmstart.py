@@ -363,7 +363,7 @@ def _summary(rows, ws):
     return out
 
 
-def run_volume(name, weights, iters_in=2, iters_ref=150, inner_ref=10, max_iters=150, inners=(5, 10),
+def run_volume(name, weights, iters_in=2, iters_ref=150, inner_ref=10, max_iters=150, inners=(5, 10, 16),
                batch=8, dev="cuda:0"):
     """Run to 1 HU on a 3D workload, with the per-slice warm start.
 
