@@ -55,7 +55,9 @@ struct GemmArgs {
     const float *bias;
     int relu;
     bf16 *y;               // E_FWD output (channels N)
-    int yup;               // E_FWD: 1 = store at output phase ab of a 2x grid
+    int yup;               // E_FWD: 1 = store at output phase ab of a 2x grid; 2 = all four
+                           // phases in one GEMM, column n = phase * yc + channel
+    int yc;                // E_FWD, yup = 2: output channels (and bias entries)
     float *o1, *o2;        // E_DG: n < oc1 -> o1 (ld oc1), else o2 (ld N - oc1)
     int oc1;
     float *part;           // E_WG partials [split][M][N]
@@ -320,7 +322,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         __syncthreads();
         bf16 *Cs = As[0];                          // BM x (BN + 8) bf16 staging (fits in 2*BM*LDK)
         constexpr int LDC = BN + 8;
-        const float bv = (col < g.N && g.bias) ? g.bias[col] : 0.0f;
+        const float bv = (col < g.N && g.bias) ? g.bias[g.yup == 2 ? col % g.yc : col] : 0.0f;
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int r = wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
@@ -334,12 +336,18 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
             const int m = m0 + r, n = n0 + cv;
             if (m >= g.M || n >= g.N) continue;
             long long pix = m;
+            int ldy = g.N, c = n;
             if (g.yup) {
-                int b, y, x;
+                int b, y, x, ab = g.ab;
+                if (g.yup == 2) {                  // 8 columns never straddle a phase (yc % 8 == 0)
+                    ab = n / g.yc;
+                    c = n - ab * g.yc;
+                    ldy = g.yc;
+                }
                 pix_decode(m, g.gH, g.gW, b, y, x);
-                pix = ((long long)b * 2 * g.gH + 2 * y + (g.ab >> 1)) * (2 * g.gW) + 2 * x + (g.ab & 1);
+                pix = ((long long)b * 2 * g.gH + 2 * y + (ab >> 1)) * (2 * g.gW) + 2 * x + (ab & 1);
             }
-            *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
+            *reinterpret_cast<bf16x8 *>(g.y + pix * ldy + c) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
         }
     } else if (EPI == E_DG) {
         if (col >= g.N) return;
@@ -954,31 +962,37 @@ __global__ void sum_double_kernel(const double *p, int n, double *out)
 
 // FP32 master weights -> bf16 forward copy and the pre-transposed
 // input-gradient copies: 3x3 [cin][tap][cout] (the gather applies the
-// negated tap offset), 2x2 [cin][phase][cout]
-__global__ void prep_conv_kernel(const float *w, bf16 *wf, bf16 *wd, int cout, int cin)
+// negated tap offset), 2x2 [cin][phase][cout].  All layers in one launch:
+// element i of the concatenated weight list belongs to the layer whose
+// prefix range holds it.
+constexpr int kPrepMax = 16;
+struct PrepTable {
+    int n;
+    long long start[kPrepMax + 1];
+    const float *src[kPrepMax];
+    bf16 *wf[kPrepMax], *wd[kPrepMax];
+    int cout[kPrepMax], cin[kPrepMax], up[kPrepMax];
+};
+__global__ void prep_all_kernel(PrepTable T)
 {
-    const long long n = (long long)cout * 9 * cin;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = (int)(i % cin);
-    const int tap = (int)((i / cin) % 9);
-    const int o = (int)(i / (9LL * cin));
-    const bf16 v = (bf16)w[i];
-    wf[i] = v;
-    wd[((long long)c * 9 + tap) * cout + o] = v;
-}
-
-__global__ void prep_up_kernel(const float *w, bf16 *wf, bf16 *wd, int cout, int cin)
-{
-    const long long n = 4LL * cout * cin;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = (int)(i % cin);
-    const int o = (int)((i / cin) % cout);
-    const int ab = (int)(i / ((long long)cout * cin));
-    const bf16 v = (bf16)w[i];
-    wf[i] = v;                                      // [ab][o][c]
-    wd[((long long)c * 4 + ab) * cout + o] = v;     // [c][ab][o]
+    if (i >= T.start[T.n]) return;
+    int L = 0;
+    while (i >= T.start[L + 1]) ++L;
+    const long long k = i - T.start[L];
+    const int cout = T.cout[L], cin = T.cin[L];
+    const int c = (int)(k % cin);
+    const bf16 v = (bf16)T.src[L][k];
+    T.wf[L][k] = v;
+    if (T.up[L]) {
+        const int o = (int)((k / cin) % cout);
+        const int ab = (int)(k / ((long long)cout * cin));
+        T.wd[L][((long long)c * 4 + ab) * cout + o] = v;     // [c][ab][o]
+    } else {
+        const int tap = (int)((k / cin) % 9);
+        const int o = (int)(k / (9LL * cin));
+        T.wd[L][((long long)c * 9 + tap) * cout + o] = v;    // [c][tap][o]
+    }
 }
 
 __global__ void adam_kernel(float *p, const float *g, float *m, float *v, long long n, float lr, float bc1,
@@ -1089,23 +1103,22 @@ hipError_t conv_fwd(lalm_unet *n, int L, const bf16 *x1, int c1, const bf16 *x2,
 hipError_t up_fwd(lalm_unet *n, int L, const bf16 *x, bf16 *y, const float *params, int B, int h, int w,
                   hipStream_t st)
 {
+    // the four output phases as one GEMM: the weights [phase][cout][cin]
+    // are a (4 cout) x cin matrix, so the input is read once
     const int cin = kLayers[L].cin, cout = kLayers[L].cout;
-    for (int ab = 0; ab < 4; ++ab) {
-        GemmArgs g{};
-        g.M = B * h * w;
-        g.N = cout;
-        g.K = cin;
-        g.a1 = x; g.ac1 = cin;
-        g.gB = B; g.gH = h; g.gW = w;
-        g.ntap = 1; g.tsign = 1; g.ab = ab;
-        g.w = n->wf[L] + (long long)ab * cout * cin;
-        g.bias = params + n->boff[L];
-        g.relu = 0;
-        g.y = y; g.yup = 1;
-        hipError_t e = gemm<A_CONV, B_W, E_FWD>(g, 1, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if (cout % 8) return hipErrorInvalidValue;
+    GemmArgs g{};
+    g.M = B * h * w;
+    g.N = 4 * cout;
+    g.K = cin;
+    g.a1 = x; g.ac1 = cin;
+    g.gB = B; g.gH = h; g.gW = w;
+    g.ntap = 1; g.tsign = 1; g.ab = -1;
+    g.w = n->wf[L];
+    g.bias = params + n->boff[L];
+    g.relu = 0;
+    g.y = y; g.yup = 2; g.yc = cout;
+    return gemm<A_CONV, B_W, E_FWD>(g, 1, st);
 }
 
 // Split-K weight-gradient GEMM (partials [split][M][N]) and the fixed-order
@@ -1227,16 +1240,21 @@ hipError_t to_dz(const float *gsrc, const bf16 *act, bf16 *dz, long long cnt, hi
 
 lalm_status prep_weights(lalm_unet *n, const float *params, hipStream_t st)
 {
+    PrepTable T{};
     for (int L = 0; L < kNL; ++L) {
         const LayerDef &l = kLayers[L];
-        if (l.kind == 0 && L != E1A) {
-            hipLaunchKernelGGL(prep_conv_kernel, dim3(nblk(wcount(l))), dim3(256), 0, st, params + n->woff[L], n->wf[L],
-                               n->wd[L], l.cout, l.cin);
-        } else if (l.kind == 1) {
-            hipLaunchKernelGGL(prep_up_kernel, dim3(nblk(wcount(l))), dim3(256), 0, st, params + n->woff[L], n->wf[L],
-                               n->wd[L], l.cout, l.cin);
-        }
+        if (!((l.kind == 0 && L != E1A) || l.kind == 1)) continue;
+        if (T.n == kPrepMax) return ufail(LALM_E_STATE, "unet weights: too many layers");
+        T.src[T.n] = params + n->woff[L];
+        T.wf[T.n] = n->wf[L];
+        T.wd[T.n] = n->wd[L];
+        T.cout[T.n] = l.cout;
+        T.cin[T.n] = l.cin;
+        T.up[T.n] = l.kind == 1;
+        T.start[T.n + 1] = T.start[T.n] + wcount(l);
+        ++T.n;
     }
+    hipLaunchKernelGGL(prep_all_kernel, dim3(nblk(T.start[T.n])), dim3(256), 0, st, T);
     UCHK("unet weights", hipGetLastError());
     return LALM_OK;
 }
