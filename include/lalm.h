@@ -263,11 +263,16 @@ LALM_API lalm_status lalm_roi_rmsd_f64(lalm_plan *plan, const float *a, const fl
 
 /*
  * Kernel timing (measurement aid, not part of the method).  While profiling
- * is on, lalm_iterate records HIP events around each of its kernels on the
- * caller's stream and accumulates their elapsed times.  lalm_profile_read
- * returns, per kernel class, the total milliseconds and launch counts since
- * lalm_profile_begin:  [0] x-update, [1] forward projection, [2]
- * back-projection with its epilogue.  ms and counts are host arrays of 3.
+ * is on, every kernel lalm_iterate launches carries start / stop HIP events
+ * on its own dispatch (on the caller's stream), and their elapsed times are
+ * summed per kernel class.  lalm_profile_read returns, per class, the total
+ * milliseconds and the number of subset steps that ran the class since
+ * lalm_profile_begin: [0] x-update (2D within a call: the step kernel that
+ * sums the partial back-projections and makes the next x candidates; also
+ * the inner FISTA iterations), [1] forward projection (with the
+ * continuation decision where it takes it), [2] back-projection (2D within
+ * a call: the line kernel; otherwise with its epilogue and, in 3D, the
+ * continuation decision).  ms and counts are host arrays of 3.
  */
 LALM_API lalm_status lalm_profile_begin(lalm_plan *plan);
 LALM_API lalm_status lalm_profile_read(lalm_plan *plan, double *ms, int64_t *counts);
