@@ -96,8 +96,10 @@ typedef struct lalm_plan lalm_plan;
  * visited in bit-reversal order; Sec. IV-B: views spread uniformly over each
  * subset).  Builds the per-view and per-ray tables in FP64 on the host,
  * stores them as FP32 on the current device, and allocates the workspace
- * (two padded image copies, one image of regularizer gradient, one subset
- * residual, reduction buffers, device scalars).
+ * (two padded image copies, one image of regularizer gradient, two partial
+ * images, one inner-iteration image, one subset residual, reduction
+ * buffers, device scalars; 2D also a second pair of padded copies, four
+ * x-candidate images and the filtered sinogram of the FBP).
  * Errors: LALM_E_INVALID for non-positive sizes, dsd <= dso, a source inside
  * the image's circumscribed cylinder, n_subsets outside [1, n_views], or an
  * unsupported detector; LALM_E_NOMEM when allocation fails.
