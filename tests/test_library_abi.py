@@ -2,6 +2,7 @@
 exports every declared call, the binding exposes the same names, and
 argument validation fails cleanly before any GPU work is queued."""
 import ctypes
+import os
 import subprocess
 
 import pytest
@@ -87,3 +88,31 @@ def test_null_arguments_rejected(lib):
     assert L.lalm_unet_create(1, 18, 16, ctypes.byref(h)) == lalm.LALM_E_INVALID   # not a multiple of 4
     from oracle import unet as U
     assert lalm.lalm_unet_param_count() == U.param_count()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets of the C struct it
+    stands for (gcc compiles a probe against the header)."""
+    from paper_1402_4381_amd import lalm
+    mirrors = {"lalm_geometry": lalm.Geometry, "lalm_problem": lalm.Problem, "lalm_state": lalm.State,
+               "lalm_options": lalm.Options, "lalm_stats": lalm.Stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lalm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0; }"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    out = subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True, check=True).stdout.split("\n")
+    got = {}
+    for l in out:
+        if l:
+            k1, k2, v = l.split()
+            got[(k1, k2)] = int(v)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
