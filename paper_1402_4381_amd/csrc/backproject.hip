@@ -143,16 +143,20 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                     const float inv = K.inv_dt / qz;     // detector rows per slice
                     const float base = wxy * rr.sc;
                     const float *rcol = A.r + (long long)kv * K.nr * K.nb + b;
+                    // slices k >= nz (a last, partial block) are computed and
+                    // dropped by the epilogue: rows are clamped, so no branch
 #pragma unroll
                     for (int t = 0; t < KZ; ++t) {
                         const int k = kb + t;
-                        if (k >= K.nz) break;
                         const int r0 = max(0, (int)ceilf(fmaf((float)(k - 1) - V.z0, inv, K.row_center) - 0.01f));
                         const int r1 = min(K.nr - 1, (int)floorf(fmaf((float)(k + 1) - V.z0, inv, K.row_center) + 0.01f));
                         // the first BP3_RW rows of the window: weights first, the
                         // residual gathers issued together (clamped rows, unused
                         // beyond r1), then accumulated in row order
-                        float wz[BP3_RW], rr[BP3_RW];
+                        // (row offsets: rows < 256 and channels < 2^24, so a
+                        // full-rate 24-bit multiply; a zero weight adds an
+                        // exact zero, so the updates need no branch)
+                        float wz[BP3_RW], rr[BP3_RW], rf[BP3_RW];
 #pragma unroll
                         for (int u = 0; u < BP3_RW; ++u) {
                             const int rw = min(r0 + u, K.nr - 1);
@@ -160,13 +164,13 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                             const float zl = floorf(zeta);
                             const float h = zeta - zl;
                             const int k0 = (int)zl;
-                            wz[u] = (r0 + u > r1) ? 0.0f : ((k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f));
-                            rr[u] = rcol[rw * K.nb];
+                            const float w = (k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f);
+                            wz[u] = (r0 + u > r1) ? 0.0f : w;
+                            rf[u] = s_rowf[rw];
+                            rr[u] = rcol[__umul24((unsigned)rw, (unsigned)K.nb)];
                         }
 #pragma unroll
-                        for (int u = 0; u < BP3_RW; ++u)
-                            if (wz[u] != 0.0f)
-                                acc[t] = fmaf(base * wz[u] * s_rowf[r0 + u], rr[u], acc[t]);
+                        for (int u = 0; u < BP3_RW; ++u) acc[t] = fmaf(base * wz[u] * rf[u], rr[u], acc[t]);
                         for (int rw = r0 + BP3_RW; rw <= r1; ++rw) {
                             const float zeta = fmaf(s_rowv[rw], qz, V.z0);
                             const float zl = floorf(zeta);
@@ -174,7 +178,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                             const int k0 = (int)zl;
                             const float w1 = (k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f);
                             if (w1 != 0.0f)
-                                acc[t] = fmaf(base * w1 * s_rowf[rw], rcol[rw * K.nb], acc[t]);
+                                acc[t] = fmaf(base * w1 * s_rowf[rw], rcol[__umul24((unsigned)rw, (unsigned)K.nb)], acc[t]);
                         }
                     }
                 }
