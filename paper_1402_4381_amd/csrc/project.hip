@@ -93,10 +93,11 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
         const int lim = ydom ? K.nx : K.ny;
         if (!IS3D) {
             const int ld = ydom ? K.ldN : K.ldT;
-            const float *base = img + 2;
             int s = s0;
+            // the slice row of sample s; in-round offsets are 32-bit
+            const float *rowp = img + 2 + (long long)s0 * ld;
             // eight samples per round: their tap loads are independent
-            for (; s + 7 <= s1; s += 8) {
+            for (; s + 7 <= s1; s += 8, rowp += 8 * ld) {
                 float v0[8], v1[8], f[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
                     const float fl = floorf(eta);
                     f[u] = eta - fl;
                     const int j0 = min(max((int)fl, -2), lim);
-                    const float *pp = base + (long long)(s + u) * ld + j0;
+                    const float *pp = rowp + (u * ld + j0);
                     v0[u] = pp[0];
                     v1[u] = pp[1];
                 }
@@ -119,20 +120,21 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
                     const float fl = floorf(eta);
                     f[u] = eta - fl;
                     const int j0 = min(max((int)fl, -2), lim);
-                    const float *pp = base + (long long)(s + u) * ld + j0;
+                    const float *pp = rowp + (u * ld + j0);
                     v0[u] = pp[0];
                     v1[u] = pp[1];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
                 s += 4;
+                rowp += 4 * ld;
             }
-            for (; s <= s1; ++s) {
+            for (; s <= s1; ++s, rowp += ld) {
                 const float eta = fmaf((float)s, rr.c, rr.a);
                 const float fl = floorf(eta);
                 const float f = eta - fl;
                 const int j0 = min(max((int)fl, -2), lim);
-                const float *pp = base + (long long)s * ld + j0;
+                const float *pp = rowp + j0;
                 const float v0 = pp[0], v1 = pp[1];
                 acc += fmaf(f, v1 - v0, v0);
             }

@@ -61,6 +61,8 @@ def _geom(**kw):
     ({}, 181),                       # more subsets than views
     (dict(dx=-1.0), 4),
     (dict(kind=7), 4),
+    (dict(n_bins=(1 << 20) + 1, ds=1e-4), 4),                 # beyond the 24-bit row offsets
+    (dict(kind=1, nz=8, n_rows=257, dt=0.01), 4),             # more than 256 detector rows
 ])
 def test_invalid_geometry_rejected_before_gpu_work(lib, kw, M):
     from paper_1402_4381_amd import lalm
