@@ -281,7 +281,9 @@ __device__ inline void splat2(float *slab, int lane_off, float fl, float flo, fl
 __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int nxt)
 {
     const GeoK &K = A.k;
-    if (A.check_status && A.sc->status) return;
+    // a stopped run (status set) skips only the writes: every read index
+    // depends on the geometry alone, so the status load need not come first
+    const int status = A.sc->status;
     __shared__ float acc[BP2_VG][BP2_ROWS][BP2_LD];
     __shared__ float4 stage[BP2_VG][BP2_WMAX];
     const int lane = threadIdx.x, wv = threadIdx.y;
@@ -373,6 +375,7 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
         }
     }
     __syncthreads();
+    if (A.check_status && status) return;
 
     // sum the waves in order and write the tile to its class's partial image
     float *outp = ypass ? A.part2 : A.part;
@@ -451,24 +454,30 @@ template <bool LAST>
 __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
 {
     const GeoK &K = A.k;
-    const DevScalars s = *A.sc;
-    if (s.status) return;
     __shared__ float tile[2][32][33];
     __shared__ double s_red[16];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + 32 * ty;
     const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
     const bool inside = i < K.nx && j < K.ny;
+    const long long idx = (long long)j * K.nx + i;
+    // the scalar record and the loads that do not depend on it go out
+    // together, before its status is tested (threads outside the image read
+    // pixel 0)
+    const DevScalars s = *A.sc;
+    const long long ldx = inside ? idx : 0;
+    const float p0 = A.part[ldx], p1 = A.part2[ldx], Go = A.G[ldx], gv = A.g[ldx];
+    const float dv = LAST ? 0.0f : A.denom[ldx];
+    // keeps the compiler from sinking those loads below the status test
+    asm volatile("" ::: "memory");
+    if (s.status) return;
     const float *xs = s.sel ? A.xs1 : A.xs0;
     const float rho = (float)s.rho;
     const bool two = A.continuation != 0;
     double part = 0.0;
     float v0 = 0.0f, v1 = 0.0f;
     if (inside) {
-        const long long idx = (long long)j * K.nx + i;
-        const float total = A.part[idx] + A.part2[idx];
-        const float Gn = A.scale * total;
-        const float Go = A.G[idx], gv = A.g[idx];
+        const float Gn = A.scale * (p0 + p1);
         part = ((double)gv - (double)Gn) * ((double)Gn - (double)Go);
         const float gn = fmaf(rho, Gn, gv) / (rho + 1.0f);
         A.G[idx] = Gn;
@@ -479,7 +488,6 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
         if (LAST) {
             A.gradR[idx] = rv;
         } else {
-            const float dv = A.denom[idx];
             const float curv = A.beta * reg_curv_sum(K, i, j, 0);
             const float alpha = (float)s.alpha;
             const long long n_idx = (long long)j * K.ldN + i + 2;

@@ -38,6 +38,31 @@ struct FPArgs {
 };
 
 constexpr int FP3_U = 8;   // 3D: samples whose taps are loaded together
+constexpr int FP2_U = 8;   // 2D: samples per round of the main loop (12, 16 and 24 measured slower)
+
+// U consecutive samples s..s+U-1 of a 2D ray: their tap pairs are loaded
+// before any is used, and the interpolated values are added in sample order.
+// rowp points at slice row s of the layout; in-round offsets stay 32-bit.
+template <int U>
+__device__ __forceinline__ void fp2d_round(float &acc, int s, const float *rowp, const RayRec &rr,
+                                           int ld, int lim)
+{
+    float v0[U], v1[U], f[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float eta = fmaf((float)(s + u), rr.c, rr.a);
+        const float fl = floorf(eta);
+        f[u] = eta - fl;
+        const int j0 = min(max((int)fl, -2), lim);
+        const float *pp = rowp + (u * ld + j0);
+        v0[u] = pp[0];
+        v1[u] = pp[1];
+    }
+    // keep the scheduler from interleaving the loads with the sums below
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
+}
 
 template <bool IS3D, int NSEG, int MODE, bool DEC>
 __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
@@ -96,36 +121,12 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
             int s = s0;
             // the slice row of sample s; in-round offsets are 32-bit
             const float *rowp = img + 2 + (long long)s0 * ld;
-            // eight samples per round: their tap loads are independent
-            for (; s + 7 <= s1; s += 8, rowp += 8 * ld) {
-                float v0[8], v1[8], f[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const float eta = fmaf((float)(s + u), rr.c, rr.a);
-                    const float fl = floorf(eta);
-                    f[u] = eta - fl;
-                    const int j0 = min(max((int)fl, -2), lim);
-                    const float *pp = rowp + (u * ld + j0);
-                    v0[u] = pp[0];
-                    v1[u] = pp[1];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
-            }
-            if (s + 3 <= s1) {                 // four of the remaining samples together
-                float v0[4], v1[4], f[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float eta = fmaf((float)(s + u), rr.c, rr.a);
-                    const float fl = floorf(eta);
-                    f[u] = eta - fl;
-                    const int j0 = min(max((int)fl, -2), lim);
-                    const float *pp = rowp + (u * ld + j0);
-                    v0[u] = pp[0];
-                    v1[u] = pp[1];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
+            // FP2_U samples per round, then 4: the tap loads of a round are
+            // independent and go out together
+            for (; s + FP2_U - 1 <= s1; s += FP2_U, rowp += FP2_U * ld)
+                fp2d_round<FP2_U>(acc, s, rowp, rr, ld, lim);
+            if (s + 3 <= s1) {
+                fp2d_round<4>(acc, s, rowp, rr, ld, lim);
                 s += 4;
                 rowp += 4 * ld;
             }
