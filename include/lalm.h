@@ -102,8 +102,9 @@ typedef struct lalm_plan lalm_plan;
  * x-candidate images and the filtered sinogram of the FBP).
  * Errors: LALM_E_INVALID for non-positive sizes, dsd <= dso, a source inside
  * the image's circumscribed cylinder, n_subsets outside [1, n_views], an
- * unsupported detector, or more than 256 detector rows or 2^20 channels;
- * LALM_E_NOMEM when allocation fails.
+ * unsupported detector, more than 256 detector rows or 2^20 channels, or
+ * (cone beam) a subset sinogram of 4 GiB or more; LALM_E_NOMEM when
+ * allocation fails.
  */
 LALM_API lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_subsets, lalm_plan **out);
 

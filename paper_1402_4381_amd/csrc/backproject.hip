@@ -107,6 +107,12 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
     const float bxc = fmaf((float)(blockIdx.x * 32) + 15.5f, K.dx, K.x0);
     const float byc = fmaf((float)(blockIdx.y * 8) + 3.5f, K.dy, K.y0);
     const float bhd = sqrtf(256.0f * K.dx * K.dx + 16.0f * K.dy * K.dy) + K.dmax;
+    // row windows of a slice, widened by 0.01 rows for rounding
+    const float rc_lo = K.row_center - 0.01f, rc_hi = K.row_center + 0.01f;
+    // residual rows are gathered by 32-bit byte offsets from the subset's base
+    // (the plan keeps a subset's residual below 4 GiB)
+    const char *rbase = (const char *)A.r;
+    const unsigned nb4 = 4u * (unsigned)K.nb;
     if (inside) {
         const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
         for (int kv = 0; kv < A.nview; ++kv) {
@@ -142,43 +148,43 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                     const float qz = fmaf((float)s, rz.k, rz.m);
                     const float inv = K.inv_dt / qz;     // detector rows per slice
                     const float base = wxy * rr.sc;
-                    const float *rcol = A.r + (long long)kv * K.nr * K.nb + b;
+                    // byte offset of (view kv, row 0, channel b)
+                    const unsigned cb = 4u * (unsigned)(kv * K.nr * K.nb + b);
                     // slices k >= nz (a last, partial block) are computed and
                     // dropped by the epilogue: rows are clamped, so no branch
 #pragma unroll
                     for (int t = 0; t < KZ; ++t) {
                         const int k = kb + t;
-                        const int r0 = max(0, (int)ceilf(fmaf((float)(k - 1) - V.z0, inv, K.row_center) - 0.01f));
-                        const int r1 = min(K.nr - 1, (int)floorf(fmaf((float)(k + 1) - V.z0, inv, K.row_center) + 0.01f));
+                        const float kf = (float)k;
+                        const int r0 = max(0, (int)ceilf(fmaf((float)(k - 1) - V.z0, inv, rc_lo)));
+                        const int r1 = min(K.nr - 1, (int)floorf(fmaf((float)(k + 1) - V.z0, inv, rc_hi)));
                         // the first BP3_RW rows of the window: weights first, the
                         // residual gathers issued together (clamped rows, unused
                         // beyond r1), then accumulated in row order
-                        // (row offsets: rows < 256 and channels < 2^24, so a
-                        // full-rate 24-bit multiply; a zero weight adds an
-                        // exact zero, so the updates need no branch)
+                        // (row offsets: rows < 256 and 4 x channels < 2^24, so
+                        // a full-rate 24-bit multiply-add; a zero weight adds
+                        // an exact zero, so the updates need no branch).  The
+                        // linear-interpolation weight of a row at slice
+                        // coordinate zeta on slice k is the tent 1 - |zeta - k|
+                        // clipped at 0.
                         float wz[BP3_RW], rr[BP3_RW], rf[BP3_RW];
 #pragma unroll
                         for (int u = 0; u < BP3_RW; ++u) {
                             const int rw = min(r0 + u, K.nr - 1);
                             const float zeta = fmaf(s_rowv[rw], qz, V.z0);
-                            const float zl = floorf(zeta);
-                            const float h = zeta - zl;
-                            const int k0 = (int)zl;
-                            const float w = (k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f);
+                            const float w = fmaxf(0.0f, 1.0f - fabsf(zeta - kf));
                             wz[u] = (r0 + u > r1) ? 0.0f : w;
                             rf[u] = s_rowf[rw];
-                            rr[u] = rcol[__umul24((unsigned)rw, (unsigned)K.nb)];
+                            rr[u] = *(const float *)(rbase + ((unsigned)__umul24((unsigned)rw, nb4) + cb));
                         }
 #pragma unroll
                         for (int u = 0; u < BP3_RW; ++u) acc[t] = fmaf(base * wz[u] * rf[u], rr[u], acc[t]);
                         for (int rw = r0 + BP3_RW; rw <= r1; ++rw) {
                             const float zeta = fmaf(s_rowv[rw], qz, V.z0);
-                            const float zl = floorf(zeta);
-                            const float h = zeta - zl;
-                            const int k0 = (int)zl;
-                            const float w1 = (k0 == k) ? (1.0f - h) : ((k0 + 1 == k) ? h : 0.0f);
+                            const float w1 = fmaxf(0.0f, 1.0f - fabsf(zeta - kf));
                             if (w1 != 0.0f)
-                                acc[t] = fmaf(base * w1 * s_rowf[rw], rcol[__umul24((unsigned)rw, (unsigned)K.nb)], acc[t]);
+                                acc[t] = fmaf(base * w1 * s_rowf[rw],
+                                              *(const float *)(rbase + ((unsigned)__umul24((unsigned)rw, nb4) + cb)), acc[t]);
                         }
                     }
                 }

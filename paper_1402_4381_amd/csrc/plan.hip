@@ -142,8 +142,12 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     if (g.kind == LALM_CONE_HELICAL && !(g.pitch >= 0)) return invalid("geometry: negative pitch");
     if (n_subsets < 1 || n_subsets > g.n_views) return invalid("n_subsets must lie in [1, n_views]");
     if (g.n_rows > 256) return invalid("geometry: at most 256 detector rows");
-    // the cone back-projector forms row offsets row * n_bins with 24-bit multiplies
+    // the cone back-projector forms row offsets row * n_bins with 24-bit
+    // multiplies and gathers a subset's residual by 32-bit byte offsets
     if (g.n_bins > (1 << 20)) return invalid("geometry: at most 2^20 detector channels");
+    if (g.kind != LALM_FAN2D &&
+        4.0 * ((g.n_views + n_subsets - 1) / n_subsets) * g.n_rows * g.n_bins >= 4294967296.0)
+        return invalid("geometry: a subset's sinogram must stay below 4 GiB");
     double half_fan = 0.5 * g.n_bins * g.ds / g.dsd;
     if (!(half_fan < 0.75)) return invalid("geometry: fan angle too wide (half fan must stay below 0.75 rad)");
 

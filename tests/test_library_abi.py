@@ -63,7 +63,8 @@ def _geom(**kw):
     (dict(kind=7), 4),
     (dict(n_bins=(1 << 20) + 1, ds=1e-4), 4),                 # beyond the 24-bit row offsets
     (dict(kind=1, nz=8, n_rows=257, dt=0.01), 4),             # more than 256 detector rows
-])
+    (dict(kind=1, nz=8, n_rows=256, dt=0.01, n_bins=1 << 20, ds=1e-4, n_views=16, n_views_per_turn=16), 4),
+])                                                            # ^ a 4 GiB subset sinogram
 def test_invalid_geometry_rejected_before_gpu_work(lib, kw, M):
     from paper_1402_4381_amd import lalm
     h = ctypes.c_void_p()
