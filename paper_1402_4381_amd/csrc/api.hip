@@ -90,12 +90,14 @@ extern "C" lalm_status lalm_sqs_denom(lalm_plan *p, const float *w_full, float *
     if (!p || !w_full || !denom) return fail(LALM_E_INVALID, "lalm_sqs_denom: null argument");
     HIPCHK("sqs ones", launch_update(p, UPD_ONES, nullptr, nullptr, nullptr, nullptr, 0.0f, 0, nullptr, st));
     for (int m = 0; m < p->M; ++m) {
+        // the library's own residuals carry each ray's scale (3D)
         HIPCHK("sqs project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), nullptr,
-                                        w_full + subset_ray0(p, m), p->d_r, 0, 0, nullptr, 0, st));
+                                        w_full + subset_ray0(p, m), p->d_r, 0, 0, nullptr, 0, st, 1));
         BpEpi e{};
         e.scale = 1.0f;
         e.accumulate = m > 0;
         e.out = denom;
+        e.ray_scaled = 1;
         HIPCHK("sqs backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r, BP_PLAIN, e, st));
     }
     return LALM_OK;
@@ -143,6 +145,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     const float inv_delta2 = 1.0f / (dl * dl);
     BpEpi e{};
     e.scale = (float)M;
+    e.ray_scaled = 1;      // the residuals below come from launch_fp with ray_scaled
     e.G = s->grad;
     e.g = s->g;
     e.x = s->x;
@@ -166,7 +169,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
         const int m0 = p->order[0];
         HIPCHK("iterate init project", launch_fp(p, subset_slot0(p, m0), subset_nview(p, m0),
                                                  prob->y + subset_ray0(p, m0), prob->w + subset_ray0(p, m0),
-                                                 p->d_r, 0, 0, nullptr, 1, st));
+                                                 p->d_r, 0, 0, nullptr, 1, st, 1));
         HIPCHK("iterate init backproject", launch_bp(p, subset_slot0(p, m0), subset_nview(p, m0), p->d_r,
                                                      BP_INIT, e, st));
     } else {
@@ -226,7 +229,7 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
             else
                 HIPCHK("iterate project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m),
                                                     prob->y + subset_ray0(p, m), prob->w + subset_ray0(p, m),
-                                                    p->d_r, 0, 0, nullptr, 1, st));
+                                                    p->d_r, 0, 0, nullptr, 1, st, 1));
         }
         if (!fused) {
             ProfScope ps(p, 2, st);

@@ -79,7 +79,10 @@ __device__ inline float atan_window(float t)
 // 3D back-projection, voxel driven (the 2D one is the line kernel below):
 // each thread gathers KZ3 slices of one (x, y) column from every ray of
 // the subset whose Joseph taps land on them, then applies the epilogue.
-template <int MODE>
+// SCALED: the residual already carries each ray's scale (in-plane length
+// factor times the row's cone factor), as the library's own forward
+// projections write it.
+template <int MODE, bool SCALED>
 __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 {
     constexpr int KZ = KZ3;
@@ -91,9 +94,12 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
     const int kb = blockIdx.z * KZ;
     const bool inside = i < K.nx && j < K.ny;
 
-    __shared__ float s_rowv[256], s_rowf[256];
+    // detector rows (v_r, cone factor); two padding rows far outside every
+    // slice carry zero weight, so a window may run up to two rows past the last
+    __shared__ float2 s_row[256 + 2];
     __shared__ double s_red[4];
-    for (int t = tid; t < K.nr; t += 256) { s_rowv[t] = A.rowv[t]; s_rowf[t] = A.rowf[t]; }
+    for (int t = tid; t < K.nr; t += 256) s_row[t] = make_float2(A.rowv[t], A.rowf[t]);
+    if (tid < 2) s_row[K.nr + tid] = make_float2(1.0e30f, 0.0f);
     __syncthreads();
 
     float acc[KZ];
@@ -115,6 +121,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
     const unsigned nb4 = 4u * (unsigned)K.nb;
     if (inside) {
         const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
+        const float fi = (float)i, fj = (float)j;
         for (int kv = 0; kv < A.nview; ++kv) {
             const ViewRec V = A.views[kv];
             {
@@ -136,18 +143,22 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
             for (int b = b0; b <= b1; ++b) {
                 const RayRec rr = R[b];
                 const bool ydom = meta_ydom(rr.meta);
-                const int s = ydom ? j : i, o = ydom ? i : j;
-                const float eta = fmaf((float)s, rr.c, rr.a);
-                const float fl = floorf(eta);
-                const float f = eta - fl;
-                const int j0 = (int)fl;
-                const float wxy = (j0 == o) ? (1.0f - f) : ((j0 + 1 == o) ? f : 0.0f);
+                // the ray's in-plane interpolation weight on this column: the
+                // tent 1 - |eta - o| clipped at 0
+                const float fs = ydom ? fj : fi, fo = ydom ? fi : fj;
+                const float eta = fmaf(fs, rr.c, rr.a);
+                const float wxy = fmaxf(0.0f, 1.0f - fabsf(eta - fo));
                 if (wxy == 0.0f) continue;
                 {
                     const RayRecZ rz = A.raysz[(long long)kv * K.nb + b];
-                    const float qz = fmaf((float)s, rz.k, rz.m);
-                    const float inv = K.inv_dt / qz;     // detector rows per slice
-                    const float base = wxy * rr.sc;
+                    const float qz = fmaf(fs, rz.k, rz.m);
+                    // detector rows per slice (it only places the row windows,
+                    // which carry a 0.01-row margin)
+                    const float inv = __fdividef(K.inv_dt, qz);
+                    // row of slice coordinate k -+ 1: (k -+ 1 - z0) inv + rc
+                    //   = -zk inv + (rc -+ inv), with zk = z0 - k
+                    const float c_lo = rc_lo - inv, c_hi = rc_hi + inv;
+                    const float base = SCALED ? wxy : wxy * rr.sc;
                     // byte offset of (view kv, row 0, channel b)
                     const unsigned cb = 4u * (unsigned)(kv * K.nr * K.nb + b);
                     // slices k >= nz (a last, partial block) are computed and
@@ -155,37 +166,43 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 #pragma unroll
                     for (int t = 0; t < KZ; ++t) {
                         const int k = kb + t;
-                        const float kf = (float)k;
-                        const int r0 = max(0, (int)ceilf(fmaf((float)(k - 1) - V.z0, inv, rc_lo)));
-                        const int r1 = min(K.nr - 1, (int)floorf(fmaf((float)(k + 1) - V.z0, inv, rc_hi)));
+                        const float zk = V.z0 - (float)k;   // zeta - k = v_r qz + zk
+                        // r0 <= nr: rows r0, r0 + 1 exist in s_row
+                        const int r0 = min(max(0, (int)ceilf(fmaf(-zk, inv, c_lo))), K.nr);
+                        const int r1 = min(K.nr - 1, (int)floorf(fmaf(-zk, inv, c_hi)));
                         // the first BP3_RW rows of the window: weights first, the
-                        // residual gathers issued together (clamped rows, unused
-                        // beyond r1), then accumulated in row order
+                        // residual gathers issued together (clamped row for the
+                        // gather; rows past r1 lie at or beyond slice k + 1, or
+                        // are padding, so their weight is zero), then accumulated
+                        // in row order
                         // (row offsets: rows < 256 and 4 x channels < 2^24, so
                         // a full-rate 24-bit multiply-add; a zero weight adds
                         // an exact zero, so the updates need no branch).  The
                         // linear-interpolation weight of a row at slice
                         // coordinate zeta on slice k is the tent 1 - |zeta - k|
                         // clipped at 0.
-                        float wz[BP3_RW], rr[BP3_RW], rf[BP3_RW];
+                        // The rows' weighted residuals are summed in row order,
+                        // then scaled by the in-plane weight once.
+                        float wz[BP3_RW], rr[BP3_RW];
 #pragma unroll
                         for (int u = 0; u < BP3_RW; ++u) {
+                            const float2 rowq = s_row[r0 + u];
                             const int rw = min(r0 + u, K.nr - 1);
-                            const float zeta = fmaf(s_rowv[rw], qz, V.z0);
-                            const float w = fmaxf(0.0f, 1.0f - fabsf(zeta - kf));
-                            wz[u] = (r0 + u > r1) ? 0.0f : w;
-                            rf[u] = s_rowf[rw];
+                            const float w = fmaxf(0.0f, 1.0f - fabsf(fmaf(rowq.x, qz, zk)));
+                            wz[u] = SCALED ? w : w * rowq.y;
                             rr[u] = *(const float *)(rbase + ((unsigned)__umul24((unsigned)rw, nb4) + cb));
                         }
+                        float sum = wz[0] * rr[0];
 #pragma unroll
-                        for (int u = 0; u < BP3_RW; ++u) acc[t] = fmaf(base * wz[u] * rf[u], rr[u], acc[t]);
+                        for (int u = 1; u < BP3_RW; ++u) sum = fmaf(wz[u], rr[u], sum);
                         for (int rw = r0 + BP3_RW; rw <= r1; ++rw) {
-                            const float zeta = fmaf(s_rowv[rw], qz, V.z0);
-                            const float w1 = fmaxf(0.0f, 1.0f - fabsf(zeta - kf));
+                            const float2 rowq = s_row[rw];
+                            const float w1 = fmaxf(0.0f, 1.0f - fabsf(fmaf(rowq.x, qz, zk)));
                             if (w1 != 0.0f)
-                                acc[t] = fmaf(base * w1 * s_rowf[rw],
-                                              *(const float *)(rbase + ((unsigned)__umul24((unsigned)rw, nb4) + cb)), acc[t]);
+                                sum = fmaf(SCALED ? w1 : w1 * rowq.y,
+                                           *(const float *)(rbase + ((unsigned)__umul24((unsigned)rw, nb4) + cb)), sum);
                         }
+                        acc[t] = fmaf(base, sum, acc[t]);
                     }
                 }
             }
@@ -552,12 +569,19 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, l
     if (tid == 0) *out = continuation_update(s, C, total, MODE == BP_INIT, true);
 }
 
-hipError_t bp_dispatch(const lalm_plan *p, const BPArgs &a, int mode, dim3 grd, hipStream_t st)
+template <bool SCALED>
+hipError_t bp_dispatch_scaled(const lalm_plan *p, const BPArgs &a, int mode, dim3 grd, hipStream_t st)
 {
     dim3 blk(32, 8);
-    if (mode == BP_PLAIN) return klaunch(p, bp_kernel<BP_PLAIN>, grd, blk, st, a);
-    if (mode == BP_INIT) return klaunch(p, bp_kernel<BP_INIT>, grd, blk, st, a);
-    return klaunch(p, bp_kernel<BP_STEP>, grd, blk, st, a);
+    if (mode == BP_PLAIN) return klaunch(p, bp_kernel<BP_PLAIN, SCALED>, grd, blk, st, a);
+    if (mode == BP_INIT) return klaunch(p, bp_kernel<BP_INIT, SCALED>, grd, blk, st, a);
+    return klaunch(p, bp_kernel<BP_STEP, SCALED>, grd, blk, st, a);
+}
+
+hipError_t bp_dispatch(const lalm_plan *p, const BPArgs &a, int mode, dim3 grd, hipStream_t st)
+{
+    return a.e.ray_scaled ? bp_dispatch_scaled<true>(p, a, mode, grd, st)
+                          : bp_dispatch_scaled<false>(p, a, mode, grd, st);
 }
 
 template <bool IS3D>

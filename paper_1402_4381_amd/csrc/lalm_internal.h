@@ -339,9 +339,12 @@ inline hipError_t klaunch(const lalm_plan *p, K kernel, dim3 grid, dim3 block, h
 // Forward projection of the subset starting at slot `slot0` holding `nview`
 // views.  mode 0: out = w .* (A x - y) (y, w may be null);
 // mode 1: accumulate 1/2 sum w (A x - y)^2 into partials[part_off + block].
+// ray_scaled (3D, mode 0): each ray's entry is further multiplied by the
+// ray's scale (in-plane length factor times the row's cone factor), which a
+// back-projection with BpEpi::ray_scaled then leaves out.
 hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *y,
                      const float *w, float *out, int mode, int64_t part_off,
-                     int64_t *n_blocks_out, int check_status, hipStream_t st);
+                     int64_t *n_blocks_out, int check_status, hipStream_t st, int ray_scaled = 0);
 
 inline lalm::DevScalars *cur_sc(const lalm_plan *p) { return p->d_sc + p->sc_cur; }
 // The same forward projection, first taking the continuation decision of
@@ -362,6 +365,7 @@ struct BpEpi {
     const float *x;        // INIT/STEP: image for grad R
     float beta, inv_delta2;   // regularizer: beta, 1/delta^2
     ContArgs cont;
+    int ray_scaled;        // 3D: r already carries each ray's scale (launch_fp ray_scaled)
 };
 // BP_INIT includes its finite check (the scalars advance); BP_STEP leaves
 // the continuation decision of the step to the next x-update or to

@@ -35,6 +35,7 @@ struct FPArgs {
     const double *dec_part;
     long long dec_n;
     ContArgs cont;
+    int ray_scaled;         // 3D mode 0: out also carries the ray's scale
 };
 
 constexpr int FP3_U = 8;   // 3D: samples whose taps are loaded together
@@ -210,9 +211,10 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
     }
     float val = 0.0f;
     if (valid) {
-        const float proj = acc * rr.sc * (IS3D ? A.rowf[r] : 1.0f);
+        const float rowf = IS3D ? A.rowf[r] : 1.0f;
+        const float proj = acc * rr.sc * rowf;
         val = proj - yv;
-        if (MODE == 0) A.out[q] = wv * val;
+        if (MODE == 0) A.out[q] = (IS3D && A.ray_scaled) ? wv * val * (rr.sc * rowf) : wv * val;
     }
     if (MODE == 1) {
         // 1/2 w e^2 summed in FP64 over the block's rays (one wavefront)
@@ -475,7 +477,7 @@ __global__ void __launch_bounds__(256) bb_finalize_kernel(const double *part, De
 
 hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
                      float *out, int mode, int64_t part_off, int64_t *n_blocks_out,
-                     int check_status, hipStream_t st)
+                     int check_status, hipStream_t st, int ray_scaled)
 {
     FPArgs a;
     a.k = p->k;
@@ -498,6 +500,7 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.dec_part = nullptr;
     a.dec_n = 0;
     a.cont = ContArgs{};
+    a.ray_scaled = ray_scaled;
     long long nblk = (a.nrays + 63) / 64;
     if (n_blocks_out) *n_blocks_out = nblk;
     if (nblk == 0) return hipSuccess;
@@ -531,6 +534,7 @@ hipError_t launch_fp_decide(const lalm_plan *p, int64_t slot0, int nview, const 
     a.dec_part = p->d_partials;
     a.dec_n = p->bp_nblocks;
     a.cont = cont;
+    a.ray_scaled = 0;       // 2D residuals carry no ray scale
     const long long nblk = (a.nrays + 63) / 64;
     if (nblk == 0) return hipErrorInvalidValue;     // every subset holds a view
     const hipError_t e = fp_dispatch<false>(p, a, p->fp_nseg, 2, nblk, st);
