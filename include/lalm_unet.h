@@ -3,7 +3,7 @@
  *
  * Not part of the paper's method: a small 2D U-Net maps an image after a
  * few OS-LALM iterations to an estimate of the image after many iterations;
- * plain OS-LALM remains the fallback and the judge (its cost value decides
+ * plain OS-LALM remains the fallback and the arbiter (its cost value decides
  * whether the estimate is kept, and the RMS difference to x* is the figure
  * of merit).  Architecture (3 levels, 3x3 convolutions + ReLU, 2x2 max
  * pooling, 2x2 stride-2 transposed convolutions, skip concatenations, 1x1

@@ -2,7 +2,7 @@
 
 The warm start is not in the paper: it is a small 2D U-Net that maps an image
 after a few OS-LALM iterations to the image after many iterations; plain
-OS-LALM stays the fallback and the judge (by its cost value and by the RMS
+OS-LALM stays the fallback and the arbiter (by its cost value and by the RMS
 difference to x*).  Architecture (3 levels, 3x3 convolutions, ReLU):
 
     e1a 1->32, e1b 32->32  | pool 2x2 | e2a 32->64, e2b 64->64 | pool 2x2 |

@@ -18,7 +18,7 @@ runs through the library's C ABI on one GPU:
   30 plain iterations; RMS difference to x* (one-subset OS-LALM with
   continuation run to convergence) over the ROI and wall time to 1 HU.
 
-Plain OS-LALM stays the fallback and the judge: the network only proposes a
+Plain OS-LALM stays the fallback and the arbiter: the network only proposes a
 starting image and the method's own cost decides whether it is used.
 """
 import argparse
