@@ -491,10 +491,16 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
     const long long ldx = inside ? idx : 0;
     const float p0 = A.part[ldx], p1 = A.part2[ldx], Go = A.G[ldx], gv = A.g[ldx];
     const float dv = LAST ? 0.0f : A.denom[ldx];
+    // the neighbourhoods of both candidates for x: the record's choice is
+    // not known yet
+    const Nbr2d n0 = load_nbr2d(K, A.xs0, i, j);
+    const Nbr2d n1 = load_nbr2d(K, A.xs1, i, j);
     // keeps the compiler from sinking those loads below the status test
     asm volatile("" ::: "memory");
     if (s.status) return;
-    const float *xs = s.sel ? A.xs1 : A.xs0;
+    Nbr2d nx;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) nx.v[t] = s.sel ? n1.v[t] : n0.v[t];
     const float rho = (float)s.rho;
     const bool two = A.continuation != 0;
     double part = 0.0;
@@ -505,8 +511,8 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
         const float gn = fmaf(rho, Gn, gv) / (rho + 1.0f);
         A.G[idx] = Gn;
         A.g[idx] = gn;
-        const float rv = reg_grad_at<false>(K, xs, i, j, 0, A.beta, A.inv_delta2);
-        const float xv = xs[idx];
+        const float rv = reg_grad_2d(K, nx, i, j, A.beta, A.inv_delta2);
+        const float xv = nx.v[4];
         if (A.xw) A.xw[idx] = xv;
         if (LAST) {
             A.gradR[idx] = rv;

@@ -182,6 +182,50 @@ __device__ inline float reg_grad_at(const GeoK &K, const float *x, int i, int j,
     return beta * s;
 }
 
+// 2D: the 3x3 neighbourhood of pixel (i, j), loaded with indices clamped
+// into the image (every load is in bounds; neighbours outside are dropped by
+// reg_grad_2d), so the loads can be issued before it is known which image
+// they will serve.  v[4] is the centre; v[3 (dy + 1) + (dx + 1)].
+struct Nbr2d {
+    float v[9];
+};
+__device__ inline Nbr2d load_nbr2d(const GeoK &K, const float *x, int i, int j)
+{
+    Nbr2d n;
+    const int ic = min(max(i, 0), K.nx - 1), jc = min(max(j, 0), K.ny - 1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int jj = min(max(jc + dy, 0), K.ny - 1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ii = min(max(ic + dx, 0), K.nx - 1);
+            n.v[3 * (dy + 1) + (dx + 1)] = x[(long long)jj * K.nx + ii];
+        }
+    }
+    return n;
+}
+// reg_grad_at<false> from a loaded neighbourhood: the same terms in the same
+// order, so the result is bit-identical.
+__device__ inline float reg_grad_2d(const GeoK &K, const Nbr2d &n, int i, int j, float beta, float inv_delta2)
+{
+    const float r2 = 0.70710678118654752f;
+    const float xc = n.v[4];
+    float s = 0.0f;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const int ii = i + dx, jj = j + dy;
+            const bool in = ii >= 0 && ii < K.nx && jj >= 0 && jj < K.ny;
+            const float kap = (dx != 0 && dy != 0) ? r2 : 1.0f;
+            const float t = fmaf(kap, dpsi(xc - n.v[3 * (dy + 1) + (dx + 1)], inv_delta2), s);
+            s = in ? t : s;
+        }
+    }
+    return beta * s;
+}
+
 // Number-weighted neighbour sum 2 * sum_{k in N(j)} kappa_jk for voxel (i,j,k)
 // (the separable majorizer curvature of the hyperbola regularizer over beta).
 __device__ inline float reg_curv_sum(const GeoK &K, int i, int j, int k)
