@@ -163,8 +163,11 @@ def _gpu_problem(L, cfg, M, data):
     return plan, y, w, denom
 
 
-@pytest.mark.parametrize("name,over,M", [CASES[0], CASES[3], CASES[5]])
+@pytest.mark.parametrize("name,over,M", [CASES[0], CASES[1], CASES[3], CASES[5], CASES[6]])
 def test_sqs_denominator_and_cost(L, name, over, M):
+    """D_L = A^T (w .* A 1) and the FP64 cost.  In 3D the library's own
+    projection pair passes residuals that already carry each ray's scale, so
+    the cone cases check that path against the oracle's plain A^T W A 1."""
     cfg = synth.get_config(name, **over)
     data = _problem(cfg)
     plan, y, w, denom = _gpu_problem(L, cfg, M, data)
