@@ -119,10 +119,33 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
     // (the plan keeps a subset's residual below 4 GiB)
     const char *rbase = (const char *)A.r;
     const unsigned nb4 = 4u * (unsigned)K.nb;
+    // helical subsets: z0 never decreases along the slots, so the views that
+    // can reach the block's slices form one range, found by two binary
+    // searches.  The bound uses tmax <= dso + |block centre| + bhd, so every
+    // view left out is one the per-view test below skips as well.
+    int kv_lo = 0, kv_hi = A.nview;
+    if (K.z_sorted) {
+        const float rmax = fmaf(K.zreach, K.dso + sqrtf(fmaf(bxc, bxc, byc * byc)) + bhd, 1.01f) + 1.0f;
+        const float zlo = (float)kb - rmax, zhi = (float)(kb + KZ - 1) + rmax;
+        int lo = 0, hi = A.nview;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (A.views[mid].z0 < zlo) lo = mid + 1;
+            else hi = mid;
+        }
+        kv_lo = lo;
+        hi = A.nview;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (A.views[mid].z0 <= zhi) lo = mid + 1;
+            else hi = mid;
+        }
+        kv_hi = lo;
+    }
     if (inside) {
         const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
         const float fi = (float)i, fj = (float)j;
-        for (int kv = 0; kv < A.nview; ++kv) {
+        for (int kv = kv_lo; kv < kv_hi; ++kv) {
             const ViewRec V = A.views[kv];
             {
                 const float tmax = sqrtf((bxc - V.sx) * (bxc - V.sx) + (byc - V.sy) * (byc - V.sy)) + bhd;

@@ -70,6 +70,8 @@ struct GeoK {
     float row_center;         // (nr-1)/2
     float bin_margin;         // channel-window margin (bins) for rounding and the window atan
     float zreach;             // 3D: ((nr-1)/2 dt) / (dsd dz), slices reached per mm of in-plane path
+    float dso;                // source to isocentre (mm)
+    int z_sorted;             // 3D: z0 never decreases along the slots of a subset (helical)
     // padded image copies
     int ldT, ldN;             // padded length of the fastest axis: ny+4, nx+4
     long long slabT, slabN;   // elements per slice of the dominant axis

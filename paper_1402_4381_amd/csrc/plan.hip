@@ -289,6 +289,17 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     K.row_center = (float)((nr - 1) / 2.0);
     K.bin_margin = (float)(0.05 + (g.dsd / g.ds) * 4e-6);
     K.zreach = (float)(((nr - 1) / 2.0 * g.dt) / (g.dsd * g.dz) * 1.0001);
+    K.dso = (float)g.dso;
+    // helical: the views of a subset are in increasing order, so their
+    // source heights never decrease; checked on the stored values
+    K.z_sorted = 0;
+    if (g.kind == LALM_CONE_HELICAL) {
+        bool sorted = true;
+        for (int m = 0; m < M && sorted; ++m)
+            for (int64_t s = p->slot_offset[m] + 1; s < p->slot_offset[m + 1]; ++s)
+                if (views[s].z0 < views[s - 1].z0) { sorted = false; break; }
+        K.z_sorted = sorted ? 1 : 0;
+    }
     K.ldT = g.ny + 4;
     K.ldN = g.nx + 4;
     K.slabT = is3d ? (long long)(g.nz + 4) * K.ldT : K.ldT;
