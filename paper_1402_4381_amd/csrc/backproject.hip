@@ -193,19 +193,17 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                         // r0 <= nr: rows r0, r0 + 1 exist in s_row
                         const int r0 = min(max(0, (int)ceilf(fmaf(-zk, inv, c_lo))), K.nr);
                         const int r1 = min(K.nr - 1, (int)floorf(fmaf(-zk, inv, c_hi)));
-                        // the first BP3_RW rows of the window: weights first, the
-                        // residual gathers issued together (clamped row for the
-                        // gather; rows past r1 lie at or beyond slice k + 1, or
-                        // are padding, so their weight is zero), then accumulated
-                        // in row order
-                        // (row offsets: rows < 256 and 4 x channels < 2^24, so
-                        // a full-rate 24-bit multiply-add; a zero weight adds
-                        // an exact zero, so the updates need no branch).  The
-                        // linear-interpolation weight of a row at slice
-                        // coordinate zeta on slice k is the tent 1 - |zeta - k|
-                        // clipped at 0.
-                        // The rows' weighted residuals are summed in row order,
-                        // then scaled by the in-plane weight once.
+                        // Rows r0..r1 of the window.  The linear-interpolation
+                        // weight of a row at slice coordinate zeta on slice k is
+                        // the tent 1 - |zeta - k| clipped at 0.  The first
+                        // BP3_RW rows go without branches: weights first, their
+                        // residual gathers issued together (the gather row is
+                        // clamped; rows past r1 lie at or beyond slice k + 1, or
+                        // are padding, so their weight is zero and they add an
+                        // exact zero).  Row offsets: rows < 256 and 4 x channels
+                        // < 2^24, so a full-rate 24-bit multiply-add.  The rows'
+                        // weighted residuals are summed in row order, then
+                        // scaled by the in-plane weight once.
                         float wz[BP3_RW], rr[BP3_RW];
 #pragma unroll
                         for (int u = 0; u < BP3_RW; ++u) {
