@@ -370,3 +370,53 @@ def test_os_lalm_without_bb_is_unchanged():
     d = synth.make_problem_data(cfg, workers=1)
     a = ora.os_lalm(cfg, d["y"], d["w"], cfg["beta"], synth.configs.delta_mu(cfg), M=3, n_steps=6)
     assert np.all(a["alpha"] == 1.0)
+
+
+def test_identical_subsets_reduce_to_one_subset():
+    """Pin of the M > 1 path.  With V view angles per turn, V coprime to M,
+    M turns (n_views = M V, the angle of view v is 2 pi v / V) and the data
+    of an angle repeated in every turn, subset m = {v : v mod M = m} holds
+    every angle exactly once, so M grad l_m = grad l exactly: the subset
+    approximation of Sec. III-A is then exact, and OS-LALM with M subsets
+    must follow, subset step for subset step, the one-subset method on the
+    same data (itself pinned above against the dense gradient form and the
+    textbook u, d form) -- the same images, the same restart decisions and
+    rho values.  This pins what depends on M in the step (the factor M of the
+    subset gradient, a per-step gradient taken on a subset rather than on all
+    views); with identical subsets it cannot see which subset a step visits,
+    so the subsets' own structure is checked as well: they partition the
+    views, subset m starts at view m and steps by M (views spread uniformly
+    over the scan, Sec. IV-B), and their sizes differ by at most one."""
+    V, M = 13, 4
+    assert math.gcd(V, M) == 1
+    cfg = small2d(n_views=M * V, n_views_per_turn=V)
+    data = synth.make_problem_data(cfg, workers=1)
+    y = np.concatenate([data["y"][:V]] * M)
+    w = np.concatenate([data["w"][:V]] * M)
+    for m, views in enumerate(ora.subset_views(cfg["n_views"], M)):
+        assert sorted(int(v) % V for v in views) == list(range(V)), m
+    for n_views, Ms in ((52, 4), (53, 4), (90, 7), (24, 24), (10, 1)):
+        subs = [np.asarray(sv) for sv in ora.subset_views(n_views, Ms)]
+        allv = np.sort(np.concatenate(subs))
+        assert np.array_equal(allv, np.arange(n_views))
+        sizes = [len(sv) for sv in subs]
+        assert max(sizes) - min(sizes) <= 1
+        for m, sv in enumerate(subs):
+            assert sv[0] == m and np.all(np.diff(sv) == Ms)
+    beta, DL = _beta(cfg, w)
+    delta = synth.configs.delta_mu(cfg)
+    n_steps = 10 * M
+    rM = ora.os_lalm(cfg, y, w, beta, delta, M=M, n_steps=n_steps, denom=DL)
+    r1 = ora.os_lalm(cfg, y, w, beta, delta, M=1, n_steps=n_steps, denom=DL)
+    scale = float(np.abs(r1["x"]).max())
+    assert scale > 0
+    np.testing.assert_allclose(rM["x"], r1["x"], rtol=1e-9, atol=1e-12 * scale)
+    np.testing.assert_allclose(rM["G"], r1["G"], rtol=1e-9, atol=1e-12 * float(np.abs(r1["G"]).max()))
+    assert np.array_equal(rM["restart"], r1["restart"])
+    np.testing.assert_allclose(rM["rho"], r1["rho"], rtol=0, atol=0)
+    # the run does restart and continue, so both branches of the rule are covered
+    assert rM["restart"].any() and not rM["restart"].all()
+    # and with genuinely different subsets (data of every view kept) the two differ
+    rD = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=n_steps)
+    r1D = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=1, n_steps=n_steps)
+    assert np.abs(rD["x"] - r1D["x"]).max() > 1e-6 * scale
