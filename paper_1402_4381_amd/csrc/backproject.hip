@@ -278,8 +278,10 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 // waves of a block take interleaved views.  For a view, each lane finds the
 // channels whose rays cross its line inside the tile's band (channel
 // coordinates of the band's two end points seen from the source); the wave
-// stages the union of those rays (a, c, sc * r) in its own LDS buffer with
-// coalesced loads, then every lane walks its rays in channel order and
+// stages the union of those rays (a, c, sc * r) in its own LDS buffers with
+// coalesced loads (one array per field: the lanes of a wave read different,
+// nearby rays, and single floats keep those reads off common banks), then
+// every lane walks its rays in channel order and
 // accumulates into its own LDS column.  No two lanes write one accumulator:
 // no atomics, fixed summation order.  Waves are summed in wave order and the
 // tile is written to the partial image of its class; a pointwise epilogue
@@ -329,7 +331,7 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
     // depends on the geometry alone, so the status load need not come first
     const int status = A.sc->status;
     __shared__ float acc[BP2_VG][BP2_ROWS][BP2_LD];
-    __shared__ float4 stage[BP2_VG][BP2_WMAX];
+    __shared__ float st_a[BP2_VG][BP2_WMAX], st_c[BP2_VG][BP2_WMAX], st_v[BP2_VG][BP2_WMAX];
     const int lane = threadIdx.x, wv = threadIdx.y;
     const int tid = lane + 64 * wv;
     for (int t = tid; t < BP2_VG * BP2_ROWS * BP2_LD; t += 64 * BP2_VG) (&acc[0][0][0])[t] = 0.0f;
@@ -345,7 +347,7 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
     const int own = own_base + lane;
     const bool active = own < n_own;
     float *slab = &acc[wv][0][0];
-    float4 *st = stage[wv];
+    float *pa = st_a[wv], *pc = st_c[wv], *pv = st_v[wv];
     const float own_c = ypass ? fmaf((float)own, K.dy, K.y0) : fmaf((float)own, K.dx, K.x0);
     const float e1 = ypass ? fmaf((float)(band_base - 1), K.dx, K.x0) : fmaf((float)(band_base - 1), K.dy, K.y0);
     const float e2 = ypass ? fmaf((float)(band_base + BP2_TR), K.dx, K.x0)
@@ -386,28 +388,33 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
             wave_lds_sync();                           // previous view's readers are done
             for (int t = lane; t <= whi - wlo; t += 64) {
                 const RayRec q = R[wlo + t];
-                st[t] = make_float4(q.a, q.c, q.sc * rv[wlo + t], 0.0f);
+                pa[t] = q.a;
+                pc[t] = q.c;
+                pv[t] = q.sc * rv[wlo + t];
             }
             wave_lds_sync();
             // lanes whose window lies outside the union never happen (the
-            // union covers every lane), so st[b - wlo] stays in range
+            // union covers every lane), so index b - wlo stays in range
             int b = b0;
             for (; b + 3 <= b1; b += 4) {
-                float4 q[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) q[u] = st[b + u - wlo];
+                float qa[4], qc[4], qv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const float eta = fmaf(sf, q[u].y, q[u].x);
+                    qa[u] = pa[b + u - wlo];
+                    qc[u] = pc[b + u - wlo];
+                    qv[u] = pv[b + u - wlo];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float eta = fmaf(sf, qc[u], qa[u]);
                     const float fl = floorf(eta);
-                    splat2(slab, lane_off, fl, flo, fhi, eta - fl, q[u].z);
+                    splat2(slab, lane_off, fl, flo, fhi, eta - fl, qv[u]);
                 }
             }
             for (; b <= b1; ++b) {
-                const float4 q0 = st[b - wlo];
-                const float eta0 = fmaf(sf, q0.y, q0.x);
+                const float eta0 = fmaf(sf, pc[b - wlo], pa[b - wlo]);
                 const float fl0 = floorf(eta0);
-                splat2(slab, lane_off, fl0, flo, fhi, eta0 - fl0, q0.z);
+                splat2(slab, lane_off, fl0, flo, fhi, eta0 - fl0, pv[b - wlo]);
             }
         } else {
             for (int b = b0; b <= b1; ++b) {           // wide window: read rays directly
