@@ -291,6 +291,8 @@ constexpr int BP2_TR = 16;     // band width of a tile
 constexpr int BP2_LD = 64;     // LDS stride between accumulator rows: a row is one bank each per lane
 constexpr int BP2_ROWS = BP2_TR + 4;   // two padding rows on each side of the band
 constexpr int BP2_WMAX = 256;  // staged rays per wave and view
+// the y-pass write-out transposes the tile sums through the staging arrays
+static_assert(64 * (BP2_TR + 1) <= BP2_VG * BP2_WMAX, "transpose buffer exceeds the staging arrays");
 
 // Continuous channel coordinate of the ray from the view's source through
 // the point (px, py).  The point lies in front of the source (dc > 0).
@@ -428,19 +430,40 @@ __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int n
     __syncthreads();
     if (A.check_status && status) return;
 
-    // sum the waves in order and write the tile to its class's partial image
-    float *outp = ypass ? A.part2 : A.part;
+    // sum the waves in order and write the tile to its class's partial image;
+    // consecutive threads walk along x in global memory
+    if (!ypass) {
+        for (int t = tid; t < BP2_TR * 64; t += 64 * BP2_VG) {
+            const int bnd = t / 64, ow = t % 64;
+            const int i = own_base + ow, j = band_base + bnd;
+            if (i >= K.nx || j >= K.ny) continue;
+            const int slot = acc_slot(bnd + 2, ow);
+            float sacc = (&acc[0][0][0])[slot];
+#pragma unroll
+            for (int w2 = 1; w2 < BP2_VG; ++w2) sacc += (&acc[w2][0][0])[slot];
+            A.part[(long long)j * K.nx + i] = sacc;
+        }
+        return;
+    }
+    // y pass: x runs along the band, i.e. across accumulator rows, so the
+    // waves are summed with the lane (own) index fastest and the sums go
+    // through a transpose with a row stride of TR + 1 (the staging arrays are
+    // free by now), which keeps both LDS passes off common banks
+    float *tr = &st_a[0][0];
     for (int t = tid; t < BP2_TR * 64; t += 64 * BP2_VG) {
-        const int bnd = ypass ? (t % BP2_TR) : (t / 64);   // consecutive threads walk along x
-        const int ow = ypass ? (t / BP2_TR) : (t % 64);
-        const int i = ypass ? band_base + bnd : own_base + ow;
-        const int j = ypass ? own_base + ow : band_base + bnd;
-        if (i >= K.nx || j >= K.ny) continue;
+        const int bnd = t / 64, ow = t % 64;
         const int slot = acc_slot(bnd + 2, ow);
         float sacc = (&acc[0][0][0])[slot];
 #pragma unroll
         for (int w2 = 1; w2 < BP2_VG; ++w2) sacc += (&acc[w2][0][0])[slot];
-        outp[(long long)j * K.nx + i] = sacc;
+        tr[ow * (BP2_TR + 1) + bnd] = sacc;
+    }
+    __syncthreads();
+    for (int t = tid; t < BP2_TR * 64; t += 64 * BP2_VG) {
+        const int bnd = t % BP2_TR, ow = t / BP2_TR;
+        const int i = band_base + bnd, j = own_base + ow;
+        if (i >= K.nx || j >= K.ny) continue;
+        A.part2[(long long)j * K.nx + i] = tr[ow * (BP2_TR + 1) + bnd];
     }
 }
 
