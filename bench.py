@@ -158,7 +158,8 @@ def main():
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU: the multi-GPU path is not built (see DESIGN.md).",
+        print("bench.py runs on one GPU: the multi-GPU path (views of a subset sharded across GPUs, "
+              "one image all-reduce per subset step) is not built.",
               file=sys.stderr)
         sys.exit(2)
 
