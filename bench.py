@@ -77,6 +77,40 @@ def cpu_baseline(cfg, data, beta, delta, budget_s):
                        "subset gradient) with the FP64 oracle: %.1f s" % (n, cfg["name"], cfg["M"], dt))
 
 
+def oracle_timing(cfg, data, beta, delta, reps=5):
+    """The FP64 oracle's pieces on one workload, medians of ``reps`` warm runs
+    with the threads the OpenMP runtime gives it (OMP_NUM_THREADS): one
+    subset's forward projection and back-projection, and one OS-LALM subset
+    step (a call of two steps minus a call of one, so the initial subset
+    gradient cancels); a full iteration is M such steps."""
+    import statistics
+    import numpy as np
+    import oracle as ora
+    M = cfg["M"]
+    views = ora.subset_views(cfg["n_views"], M)[ora.bit_reversal_order(M)[1]]
+    x = np.random.default_rng(0).uniform(0.0, 0.02, ora.image_shape(cfg))
+    DL = ora.sqs_denom(cfg, data["w"])
+
+    def med(f):
+        f()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    t_fp = med(lambda: ora.forward(cfg, x, views))
+    r = ora.forward(cfg, x, views)
+    t_bp = med(lambda: ora.back(cfg, r, views))
+    t1 = med(lambda: ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=1, denom=DL))
+    t2 = med(lambda: ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=2, denom=DL))
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return dict(workload=cfg["name"], threads=threads, reps=reps, subset_views=len(views),
+                fp_subset_s=round(t_fp, 5), bp_subset_s=round(t_bp, 5), step_s=round(t2 - t1, 5),
+                iteration_s=round(M * (t2 - t1), 4), kind="oracle")
+
+
 def time_to_1hu(lalm, torch, synth, cfg, data, plan, y, w, denom, beta, delta, dev,
                 xstar_iters, max_iters, inner=(5,)):
     """Wall time of plain OS-LALM (M subsets, continuation, x0 = 0) to reach
@@ -156,6 +190,9 @@ def main():
     ap.add_argument("--max-iters-1hu", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle's projector pair and subset step (CPU; "
+                         "threads from OMP_NUM_THREADS)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the multi-GPU path (views of a subset sharded across GPUs, "
@@ -164,8 +201,13 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import synth
+    if args.oracle_timing:
+        cfg = synth.get_config(args.workload)
+        data = synth.make_problem_data(cfg)
+        print(json.dumps(oracle_timing(cfg, data, cfg["beta"], synth.configs.delta_mu(cfg))))
+        return
+    import torch
     from paper_1402_4381_amd import lalm
 
     if not torch.cuda.is_available():
