@@ -59,3 +59,15 @@ def test_source_hash_tracks_every_listed_file():
     h1 = bench.source_hash(bench.KERNEL_SOURCES["update"])
     h2 = bench.source_hash(bench.KERNEL_SOURCES["update"][:-1])
     assert h1 != h2 and len(h1) == 16
+
+
+def test_oracle_timing_mode_runs_without_a_gpu():
+    env = dict(os.environ, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-timing", "--workload", "fan2d_128"],
+                       capture_output=True, text=True, timeout=600, cwd=ROOT, env=env)
+    assert r.returncode == 0, r.stderr
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    assert rec["workload"] == "fan2d_128" and rec["threads"] == 2 and rec["reps"] == 5
+    assert rec["subset_views"] == 45
+    assert 0 < rec["fp_subset_s"] and 0 < rec["bp_subset_s"]
+    assert rec["iteration_s"] == pytest.approx(4 * rec["step_s"], rel=1e-3, abs=1e-4)
