@@ -382,7 +382,7 @@ def bb_alpha(s, yv, DL, alpha_min):
 
 def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0,
             rho_min=1e-3, x0=None, denom=None, forced_restart=None, nonneg=True,
-            callback=None, n_inner=1, bb=False, bb_alpha_min=0.01):
+            callback=None, n_inner=1, bb=False, bb_alpha_min=0.01, history=None):
     """OS-LALM, Sec. III-A eq. "os_lalm_iterates".
 
     The substitution of eq. "ct_substitution" makes grad l_m the weighted
@@ -411,6 +411,11 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     step uses rho_l.  ``forced_restart`` (bool per step) overrides the sign
     test, for replaying a restart sequence.
 
+    ``callback(j, x)`` runs after step j; ``history``, a dict, receives the
+    live per-step lists rho, xi and restart at the start (so a callback can
+    read them while the run goes on); if it holds a list under "g", the
+    split gradient g before every step and after the last is appended to it.
+
     Returns a dict with x, g, G and per-step arrays rho, xi, restart.
     """
     is3d = cfg["kind"] != 0
@@ -425,6 +430,11 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     l = 0
     rho = 1.0 if continuation else rho_fixed
     hist_rho, hist_xi, hist_rs, hist_alpha = [], [], [], []
+    keep_g = history is not None and isinstance(history.get("g"), list)
+    if history is not None:
+        history.update(rho=hist_rho, xi=hist_xi, restart=hist_rs)
+    if keep_g:
+        history["g"].append(g.copy())
     alpha, x_prev, G_prev = 1.0, None, None
     for j in range(n_steps):
         if bb and j % M == 0:
@@ -452,6 +462,8 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
             rho = rho_l(l, rho_min)
         hist_rs.append(restart)
         x, g, G = x_new, g_new, G_new
+        if keep_g:
+            history["g"].append(g.copy())
         if callback is not None:
             callback(j, x)
     return dict(x=x, g=g, G=G, rho=np.array(hist_rho), xi=np.array(hist_xi),

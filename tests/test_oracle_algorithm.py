@@ -427,3 +427,80 @@ def test_identical_subsets_reduce_to_one_subset(is3d):
     rD = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=n_steps)
     r1D = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=1, n_steps=n_steps)
     assert np.abs(rD["x"] - r1D["x"]).max() > 1e-6 * scale
+
+
+# ------------------------------------------------ pins of xi and of the cost
+
+def _dense_grad(A, y, w):
+    """grad l(x) = A'W(Ax - y) from the per-entry dense matrix."""
+    return lambda x: A.T @ (w * (A @ x - y))
+
+
+def test_restart_indicator_is_the_papers_xi_with_restarts():
+    """Sec. III-B, eq. "period_indicator_qp": with one subset the indicator
+    is (g_k - grad l(x_{k+1}))'(grad l(x_{k+1}) - grad l(x_k)), g_k the split
+    gradient before step k.  Recomputed from the dense matrix at the
+    oracle's own iterates, on a run with several natural restarts."""
+    cfg, data, A, y, w, DL = _tiny_problem()
+    shape = ora.image_shape(cfg)
+    beta = 2.0 ** -8 * float(np.median(DL[synth.roi_mask(cfg).ravel()]))
+    delta = synth.configs.delta_mu(cfg)
+    xs, hist = [np.zeros(A.shape[1])], {"g": []}
+    out = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=1, n_steps=200,
+                      callback=lambda j, x: xs.append(x.ravel().copy()), history=hist)
+    assert int(out["restart"].sum()) >= 3
+    grad = _dense_grad(A, y, w)
+    gl = [grad(x) for x in xs]
+    g = [v.ravel() for v in hist["g"]]
+    xi = np.array([(g[k] - gl[k + 1]) @ (gl[k + 1] - gl[k]) for k in range(200)])
+    scale = np.array([np.linalg.norm(g[k] - gl[k + 1]) * np.linalg.norm(gl[k + 1] - gl[k])
+                      for k in range(200)])
+    np.testing.assert_allclose(out["xi"], xi, rtol=0, atol=1e-9 * scale.max())
+    assert np.all(np.abs(out["xi"] - xi) <= 1e-9 * scale + 1e-300)
+    # the restart rule is the sign of that value (l = 0 iff xi > 0)
+    np.testing.assert_array_equal(out["restart"], xi > 0)
+    # the comparison tells apart the plausible slips: the opposite sign, the
+    # new split gradient in place of the old one, the gradient difference
+    # taken against the wrong iterate
+    for alt in (-xi,
+                np.array([(g[k + 1] - gl[k + 1]) @ (gl[k + 1] - gl[k]) for k in range(200)]),
+                np.array([(g[k] - gl[k + 1]) @ (gl[k + 1] - gl[max(k - 1, 0)]) for k in range(200)])):
+        assert np.abs(out["xi"] - alt).max() > 1e-3 * scale.max()
+
+
+def _cost_gradient_error(cost_fn, cfg, data, A, beta, delta, rng):
+    """Largest relative gap between central differences of cost_fn and
+    A'W(Ax - y) + grad R at random voxels."""
+    shape = ora.image_shape(cfg)
+    y, w = data["y"].ravel(), data["w"].ravel()
+    x = rng.uniform(0.005, 0.03, shape)
+    gexp = (A.T @ (w * (A @ x.ravel() - y))).reshape(shape) + ora.reg_grad(x, beta, delta, False)
+    h = 1e-7
+    err = 0.0
+    for _ in range(16):
+        idx = tuple(int(rng.integers(0, n)) for n in shape)
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        fd = (cost_fn(xp)[0] - cost_fn(xm)[0]) / (2 * h)
+        err = max(err, abs(fd - gexp[idx]) / max(abs(gexp[idx]), 1e-12 * np.abs(gexp).max()))
+    return err
+
+
+def test_cost_gradient_is_the_weighted_residual_back_projection():
+    """Sec. IV, eq. "ct_recon": Psi(x) = 1/2 ||y - Ax||_W^2 + R(x), so its
+    gradient is A'W(Ax - y) + grad R (dense matrix and the regularizer
+    gradient, both pinned elsewhere).  This fixes the 1/2 and the weights."""
+    cfg, data, A, y, w, DL = _tiny_problem()
+    beta, delta = 1e-3 * float(np.median(DL)), synth.configs.delta_mu(cfg)
+    cost = lambda x: ora.cost(cfg, x, data["y"], data["w"], beta, delta)
+    assert _cost_gradient_error(cost, cfg, data, A, beta, delta, np.random.default_rng(7)) < 1e-6
+    # the parts add up
+    x = np.random.default_rng(8).uniform(0.005, 0.03, ora.image_shape(cfg))
+    tot, dat, reg = cost(x)
+    assert tot == dat + reg
+    assert abs(reg - ora.reg_value(x, beta, delta, False)) <= 1e-12 * abs(reg)
+    # planted slips fail the pin: the data term without its 1/2, or unweighted
+    no_half = lambda x: (2.0 * cost(x)[1] + cost(x)[2],)
+    unweighted = lambda x: (ora.cost(cfg, x, data["y"], np.ones_like(data["w"]), beta, delta)[0],)
+    for bad in (no_half, unweighted):
+        assert _cost_gradient_error(bad, cfg, data, A, beta, delta, np.random.default_rng(7)) > 0.1

@@ -11,6 +11,7 @@
   pixelisation to discretisation accuracy, improving under refinement.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -204,3 +205,60 @@ def test_fbp_of_the_phantom_is_close_to_the_pixelized_phantom():
     m = synth.roi_mask(cfg)
     rel = np.linalg.norm((f - truth)[m]) / np.linalg.norm(truth[m])
     assert rel < 0.08
+
+
+def _brute_force_samples(cfg):
+    """Joseph samples with at least one tap in the volume, counted from the
+    per-entry dense matrix: for every ray, the number of distinct slices of
+    its dominant in-plane axis that hold a non-zero entry of its row."""
+    A = ora.dense(cfg)
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    total, q = 0, 0
+    for v in range(cfg["n_views"]):
+        for r in range(cfg["n_rows"]):
+            for b in range(cfg["n_bins"]):
+                _, u = ora.ray(cfg, v, r, b)
+                cols = np.nonzero(A[q])[0]
+                i = cols % nx
+                j = (cols // nx) % ny
+                total += len(np.unique(i if abs(u[0]) >= abs(u[1]) else j))
+                q += 1
+    assert q == A.shape[0] and nz * ny * nx == A.shape[1]
+    return total
+
+
+def _mutated_count(cfg, tmp_path, old, new):
+    """og_count_samples of a copy of the oracle's C source with one planted
+    change, compiled on the side."""
+    import ctypes
+    import subprocess
+    from oracle import oracle as _oracle_mod
+    src = open(os.path.join(os.path.dirname(_oracle_mod.__file__), "oracle.c")).read()
+    assert src.count(old) == 1
+    path = tmp_path / "mut.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-std=c99", str(path), "-o", str(lib), "-lm"])
+    L = ctypes.CDLL(str(lib))
+    views = np.arange(cfg["n_views"], dtype=np.int32)
+    L.og_count_samples.restype = ctypes.c_longlong
+    return int(L.og_count_samples(ctypes.byref(_oracle_mod._geom(cfg)),
+                                  views.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(views)))
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d", "tiny_helical"])
+def test_sample_count_equals_brute_force(name, tmp_path):
+    """The sample count behind every byte figure equals a brute-force count
+    from the per-entry weights (which equal the ray march, pinned above);
+    a count whose slice range is shifted by one differs from it."""
+    cfg = synth.get_config(name)
+    n = ora.count_samples(cfg)
+    assert n == _brute_force_samples(cfg)
+    # per view too (the GPU plan reports per subset)
+    v0 = ora.count_samples(cfg, [0]) + ora.count_samples(cfg, list(range(1, cfg["n_views"])))
+    assert v0 == n
+    # planted slips: the in-volume test of the lower tap shifted by one
+    assert _mutated_count(cfg, tmp_path, "if (lo < -1 || lo > no - 1) continue;",
+                          "if (lo < 0 || lo > no - 1) continue;") != n
+    assert _mutated_count(cfg, tmp_path, "if (lo < -1 || lo > no - 1) continue;",
+                          "if (lo < -1 || lo > no - 2) continue;") != n

@@ -129,3 +129,50 @@ def test_warmstart_layer_table_matches_the_oracle():
     f = sum(2 * np.prod(ws) * H * W_ / res[n] / (4 if n.startswith("up") else 1)
             for n, ws, _ in U.param_shapes())
     assert W.forward_flops(H, W_) == pytest.approx(f)
+
+
+def test_adam_closed_forms():
+    """Adam (Kingma & Ba) with bias correction, from zero moments:
+    * a constant gradient g gives the step lr g / (|g| + eps) at every t
+      (the corrected moments are exactly g and g^2);
+    * alternating +a, -a gives the second step lr (1 - b1)/(1 + b1) sign(a)
+      (corrected first moment -(1 - b1) a / (1 + b1), second moment a^2)."""
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    g = np.array([0.3, -2.0, 1e-3, 5.0])
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 8):
+        th_new, m, v = U.adam_step(th, g, m, v, t, lr, b1, b2, eps)
+        np.testing.assert_allclose(th_new - th, -lr * g / (np.abs(g) + eps), rtol=1e-9, atol=0)
+        th = th_new
+    a = np.array([0.7, -0.2])
+    th1, m, v = U.adam_step(np.zeros(2), a, np.zeros(2), np.zeros(2), 1, lr, b1, b2, eps)
+    np.testing.assert_allclose(th1, -lr * a / (np.abs(a) + eps), rtol=1e-12)
+    th2, m, v = U.adam_step(th1, -a, m, v, 2, lr, b1, b2, eps)
+    np.testing.assert_allclose(th2 - th1, lr * (1 - b1) / (1 + b1) * a / (np.abs(a) + eps),
+                               rtol=1e-6)
+    # a step without the bias correction fails the first closed form
+    m0 = (1 - b1) * g
+    v0 = (1 - b2) * g * g
+    uncorrected = -lr * m0 / (np.sqrt(v0) + eps)
+    assert np.abs(uncorrected + lr * g / (np.abs(g) + eps)).max() > 0.5 * lr
+
+
+def test_upconv_against_direct_scatter():
+    """2x2 stride-2 transposed convolution by its scatter definition: input
+    pixel (i, j) adds W[a, c] x[i, j] to output pixel (2i + a, 2j + c), plus
+    the bias; the output windows do not overlap at stride 2."""
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(2, 3, 4, 3))
+    w = rng.normal(size=(2, 2, 5, 3))
+    b = rng.normal(size=5)
+    ref = np.zeros((2, 6, 8, 5))
+    for n in range(2):
+        for i in range(3):
+            for j in range(4):
+                for a in range(2):
+                    for c in range(2):
+                        for o in range(5):
+                            ref[n, 2 * i + a, 2 * j + c, o] += sum(w[a, c, o, ci] * x[n, i, j, ci]
+                                                                  for ci in range(3))
+    ref += b
+    np.testing.assert_allclose(U.upconv2(x, w, b), ref, rtol=1e-12, atol=1e-12)
