@@ -37,12 +37,13 @@ def test_no_gpu_is_an_error_not_a_fallback():
     assert "needs a GPU" in r.stderr
 
 
+@pytest.mark.parametrize("wl", ["fan2d_512", "cone_helical_512x256"])
 @pytest.mark.parametrize("cls", ["backproject", "project", "update"])
-def test_traffic_records_are_complete(cls):
+def test_traffic_records_are_complete(cls, wl):
     import bench
-    path = os.path.join(ROOT, "profiles", "traffic_%s_fan2d_512.json" % cls)
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (cls, wl))
     rec = json.load(open(path))
-    assert rec["kernel_class"] == cls and rec["workload"] == "fan2d_512"
+    assert rec["kernel_class"] == cls and rec["workload"] == wl
     assert abs(rec["hbm_bytes_per_launch"] - rec["hbm_read_bytes_per_launch"] - rec["hbm_write_bytes_per_launch"]) <= 1
     assert rec["hbm_bytes_per_launch"] > 0
     assert all("rocprofv3 --pmc" in c for c in rec["commands"])
@@ -71,3 +72,16 @@ def test_oracle_timing_mode_runs_without_a_gpu():
     assert rec["subset_views"] == 45
     assert 0 < rec["fp_subset_s"] and 0 < rec["bp_subset_s"]
     assert rec["iteration_s"] == pytest.approx(4 * rec["step_s"], rel=1e-3, abs=1e-4)
+
+
+@pytest.mark.parametrize("cls", ["backproject", "project", "update"])
+def test_counter_records_of_the_default_workload(cls):
+    """The default workload's counter records carry the L2 hit rate and the
+    VALU issue use the benchmark line reports, keyed on the kernel sources."""
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "counters_%s_%s.json" % (cls, bench.DEFAULT_WORKLOAD))))
+    assert rec["kernel_class"] == cls and rec["workload"] == bench.DEFAULT_WORKLOAD
+    assert 0.0 < rec["l2_hit_rate"] < 1.0 and 0.0 < rec["valu_issue"] < 1.0
+    assert rec["l2_hits"] > 0 and rec["valu_insts_per_launch"] > 0
+    assert "rocprofv3 --pmc" in rec["command"] and "TCC_HIT_sum" in rec["command"]
+    assert rec["source"] == bench.KERNEL_SOURCES[cls] and len(rec["source_sha256_16"]) == 16
