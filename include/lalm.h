@@ -109,7 +109,10 @@ typedef struct lalm_plan lalm_plan;
 LALM_API lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_subsets, lalm_plan **out);
 
 /*
- * Plan facts, written to host arrays the caller provides (any may be NULL):
+ * Plan facts (the ordered subsets of Sec. IV-A, visited in bit-reversal
+ * order, with their views spread over the scan as Sec. IV-B asks; the
+ * Joseph sample count of every subset is the unit of the projector's work),
+ * written to host arrays the caller provides (any may be NULL):
  *   image_elems      nx*ny*nz;  sino_elems  n_views*n_rows*n_bins;
  *   subset_ray_offset [M+1] first ray (element) of each subset in the
  *                    subset-major sinogram, and the total at [M];
@@ -140,10 +143,16 @@ LALM_API lalm_status lalm_project_subset(lalm_plan *plan, int32_t m, const float
                                 const float *y_sub, const float *w_sub, hipStream_t stream);
 
 /*
- * Back-projection of subset m with the exact transpose of
- * lalm_project_subset's weights (matched adjoint, deterministic gather, no
- * atomics): x_out = scale * A_m' r (accumulate = 0) or
- * x_out += scale * A_m' r (accumulate = 1).
+ * Back-projection of subset m: the transpose A_m' of the subset system
+ * matrix, the operator of the subset gradient M grad l_m(x) =
+ * M A_m' W_m (A_m x - y_m) that every OS-LALM step evaluates (Sec. III-A,
+ * eq. "os_lalm_iterates", with the substitution of eq. "ct_substitution").
+ * Exact transpose of lalm_project_subset's weights (matched adjoint,
+ * deterministic gather, no atomics): x_out = scale * A_m' r
+ * (accumulate = 0) or x_out += scale * A_m' r (accumulate = 1).  r_sub
+ * holds the subset's rays ([view][row][bin], as lalm_project_subset's
+ * output), x_out is an image; both are caller-owned device arrays.
+ * Errors: LALM_E_INVALID for a null pointer or m outside [0, M).
  */
 LALM_API lalm_status lalm_backproject_subset(lalm_plan *plan, int32_t m, const float *r_sub, float *x_out,
                                     float scale, int32_t accumulate, hipStream_t stream);
