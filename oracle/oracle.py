@@ -414,7 +414,8 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     ``callback(j, x)`` runs after step j; ``history``, a dict, receives the
     live per-step lists rho, xi and restart at the start (so a callback can
     read them while the run goes on); if it holds a list under "g", the
-    split gradient g before every step and after the last is appended to it.
+    split gradient g before every step and after the last is appended to it,
+    and likewise the scaled subset gradient G for a list under "G".
 
     Returns a dict with x, g, G and per-step arrays rho, xi, restart.
     """
@@ -431,10 +432,13 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
     rho = 1.0 if continuation else rho_fixed
     hist_rho, hist_xi, hist_rs, hist_alpha = [], [], [], []
     keep_g = history is not None and isinstance(history.get("g"), list)
+    keep_G = history is not None and isinstance(history.get("G"), list)
     if history is not None:
         history.update(rho=hist_rho, xi=hist_xi, restart=hist_rs)
     if keep_g:
         history["g"].append(g.copy())
+    if keep_G:
+        history["G"].append(G.copy())
     alpha, x_prev, G_prev = 1.0, None, None
     for j in range(n_steps):
         if bb and j % M == 0:
@@ -464,6 +468,8 @@ def os_lalm(cfg, y, w, beta, delta, M, n_steps, continuation=True, rho_fixed=1.0
         x, g, G = x_new, g_new, G_new
         if keep_g:
             history["g"].append(g.copy())
+        if keep_G:
+            history["G"].append(G.copy())
         if callback is not None:
             callback(j, x)
     return dict(x=x, g=g, G=G, rho=np.array(hist_rho), xi=np.array(hist_xi),

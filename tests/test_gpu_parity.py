@@ -4,8 +4,10 @@ Tolerances (FP32 kernels vs FP64 oracle):
 * projections and back-projections: relative L2 error <= 1e-5 per subset,
   and max abs error <= 1e-5 x max |oracle|;
 * adjoint test on the GPU (FP32 kernels, FP64 inner products):
-  |<A x, r> - <x, A' r>| <= 1e-6 x ||A x|| ||r|| (with r of random sign the
-  inner product itself can cancel, so it is not the scale of the rounding);
+  |<A x, r> - <x, A' r>| <= 1e-6 x sum_i |(A x)_i r_i| (the size of the
+  terms the inner product sums; with r of random sign the inner product
+  itself can cancel, so it is not the scale of the rounding), on the medium
+  geometries for every subset and at full size for one subset;
 * Joseph sample counts and subset bookkeeping: exact;
 * images after a fixed number of OS-LALM iterations: ROI RMS difference
   <= 0.5 HU (free-running), also reported with the oracle's restart sequence
@@ -13,6 +15,8 @@ Tolerances (FP32 kernels vs FP64 oracle):
 * cost: relative 1e-4 (the weighted residual A x - y cancels about four
   digits of FP32 against the data).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -124,6 +128,21 @@ def test_residual_mode_and_accumulate(L, name, over, M):
     assert rel_l2(xb.cpu().numpy().reshape(want.shape), want) <= 1e-5
 
 
+def _adjoint_check(L, plan, m, xg, rg):
+    """<A_m x, r> and <x, A_m' r> (FP64 dots of the FP32 kernels' outputs)
+    and the sum of |(A_m x)_i r_i|."""
+    n = plan.subset_rays(m)
+    ax = torch.empty(n, device=DEV)
+    L.lalm_project_subset(plan, m, xg, ax)
+    atr = torch.empty(plan.image_elems, device=DEV)
+    L.lalm_backproject_subset(plan, m, rg, atr)
+    d = torch.zeros(3, dtype=torch.float64, device=DEV)
+    L.lalm_dot_f64(plan, ax, rg, d[0:1])
+    L.lalm_dot_f64(plan, xg, atr, d[1:2])
+    L.lalm_dot_f64(plan, ax.abs().contiguous(), rg.abs().contiguous(), d[2:3])
+    return d.cpu().numpy()
+
+
 @pytest.mark.parametrize("name,over,M", [CASES[3], CASES[4], CASES[5], CASES[6]])
 def test_adjoint_identity_on_gpu(L, name, over, M):
     cfg = synth.get_config(name, **over)
@@ -131,22 +150,58 @@ def test_adjoint_identity_on_gpu(L, name, over, M):
     rng = np.random.default_rng(3)
     xg = gpu(rng.uniform(0, 1, ora.image_shape(cfg))).reshape(-1)
     for m in range(M):
-        n = plan.subset_rays(m)
-        rg = gpu(rng.normal(size=n))
-        ax = torch.empty(n, device=DEV)
-        L.lalm_project_subset(plan, m, xg, ax)
-        atr = torch.empty(plan.image_elems, device=DEV)
-        L.lalm_backproject_subset(plan, m, rg, atr)
-        d = torch.zeros(4, dtype=torch.float64, device=DEV)
-        L.lalm_dot_f64(plan, ax, rg, d[0:1])
-        L.lalm_dot_f64(plan, xg, atr, d[1:2])
-        L.lalm_dot_f64(plan, ax, ax, d[2:3])
-        L.lalm_dot_f64(plan, rg, rg, d[3:4])
-        a, b, aa, rr = d.cpu().numpy()
-        scale = np.sqrt(aa * rr)            # Cauchy-Schwarz bound of <Ax, r>
-        say("  adjoint m=%d <Ax,r>=%.9e <x,A'r>=%.9e |diff|/(|Ax||r|)=%.2e"
-            % (m, a, b, abs(a - b) / scale))
-        assert abs(a - b) <= 1e-6 * scale
+        rg = gpu(rng.normal(size=plan.subset_rays(m)))
+        a, b, terms = _adjoint_check(L, plan, m, xg, rg)
+        say("  adjoint m=%d <Ax,r>=%.9e <x,A'r>=%.9e |diff|/sum|Ax_i r_i|=%.2e" % (m, a, b, abs(a - b) / terms))
+        assert abs(a - b) <= 1e-6 * terms
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name,M", [("fan2d_512", 24), ("cone_axial_512x64", 12), ("cone_helical_512x256", 12)])
+def test_adjoint_identity_full_size(L, name, M):
+    """The matched pair at full size in the benchmark's launch configuration
+    (the subset the first step projects): the 2D line kernel's staging and
+    wide-window paths, the 3D forward projector's segment split and the
+    helical view-range search all take part."""
+    cfg = synth.get_config(name)
+    say("full-size adjoint", name, "M", M)
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    rng = np.random.default_rng(4)
+    xg = gpu(rng.uniform(0, 1, ora.image_shape(cfg)).astype(np.float32)).reshape(-1)
+    m = int(plan.order[1])
+    rg = gpu(rng.normal(size=plan.subset_rays(m)).astype(np.float32))
+    a, b, terms = _adjoint_check(L, plan, m, xg, rg)
+    say("  adjoint m=%d <Ax,r>=%.12e <x,A'r>=%.12e |diff|/sum|Ax_i r_i|=%.2e" % (m, a, b, abs(a - b) / terms))
+    assert abs(a - b) <= 1e-6 * terms
+
+
+@pytest.mark.parametrize("name,over", [("fan2d_128", {}), ("cone_axial_512x64", MED3D)])
+def test_fp64_monitors_against_oracle(L, name, over):
+    """lalm_dot_f64 against the FP64 sum of the same FP32 products (a length
+    that is not a multiple of any block size) and lalm_roi_rmsd_f64 against
+    the oracle's ROI RMS difference (Sec. V) of the same FP32 images."""
+    cfg = synth.get_config(name, **over)
+    plan = L.lalm_plan_geometry(synth.geometry_of(cfg), 2)
+    rng = np.random.default_rng(21)
+    n = 1_000_003
+    a32 = rng.normal(size=n).astype(np.float32)
+    b32 = rng.normal(size=n).astype(np.float32)
+    out = torch.zeros(1, dtype=torch.float64, device=DEV)
+    L.lalm_dot_f64(plan, gpu(a32), gpu(b32), out)
+    a64, b64 = a32.astype(np.float64), b32.astype(np.float64)
+    want = float(np.dot(a64, b64))
+    terms = float(np.sum(np.abs(a64 * b64)))
+    got = float(out.item())
+    say("%s dot gpu %.15e oracle %.15e |diff|/sum|a_i b_i| %.2e" % (name, got, want, abs(got - want) / terms))
+    assert abs(got - want) <= 1e-11 * terms
+    shape = ora.image_shape(cfg)
+    x1 = rng.uniform(0.0, 0.03, shape).astype(np.float32)
+    x2 = (x1 + rng.normal(0.0, 1e-4, shape)).astype(np.float32)
+    L.lalm_roi_rmsd_f64(plan, gpu(x1).reshape(-1), gpu(x2).reshape(-1), synth.roi_radius(cfg), out)
+    got = float(out.item())
+    want = ora.rmsd_hu(x1, x2, synth.roi_mask(cfg), 1.0)
+    say("%s ROI RMSD gpu %.15e oracle %.15e" % (name, got, want))
+    assert abs(got - want) <= 1e-11 * want
 
 
 def _problem(cfg, seed=None):
@@ -236,6 +291,116 @@ def test_os_lalm_parity_free_running_and_replay(L, name, M, n_iter):
     rho_g = stats["rho"].cpu().numpy()
     if mism == 0:
         np.testing.assert_allclose(rho_g, ref["rho"], rtol=1e-12)
+
+
+def _marginal(ref, hist, tol=1e-5):
+    """Steps whose restart decision is marginal: |xi| < tol ||g - G+|| ||G+ - G||
+    (g, G before the step, G+ after it), with that product per step."""
+    g, G = hist["g"], hist["G"]
+    n = len(ref["xi"])
+    prod = np.array([np.linalg.norm(g[j] - G[j + 1]) * np.linalg.norm(G[j + 1] - G[j]) for j in range(n)])
+    return np.nonzero(np.abs(ref["xi"]) < tol * prod)[0], prod
+
+
+@pytest.mark.timeout(300)
+def test_natural_restarts_free_running_and_replay(L):
+    """One-subset OS-LALM with continuation on the 128^2 fan-beam problem
+    restarts on its own (xi > 0, Sec. III-B) several times within 40 steps.
+    Free-running, the GPU takes the same restart decisions as the FP64 oracle
+    (a mismatch is allowed only at a marginal decision, |xi| below 1e-5
+    ||g - G+|| ||G+ - G||, and the run after it is then a different valid
+    trajectory), its FP64 xi agrees with the oracle's to 1e-3 of that scale,
+    and the image is within 0.5 HU; replaying the oracle's restart bits
+    gives the same."""
+    cfg = synth.get_config("fan2d_128")
+    M, n = 1, 40
+    data = _problem(cfg)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    hist = {"g": [], "G": []}
+    ref = ora.os_lalm(cfg, data["y"], data["w"], beta, delta, M=M, n_steps=n, history=hist)
+    n_rs = int(ref["restart"].sum())
+    marg, prod = _marginal(ref, hist)
+    say("oracle: %d restarts at steps %s; %d marginal decisions %s"
+        % (n_rs, list(np.nonzero(ref["restart"])[0]), len(marg), list(marg)))
+    assert n_rs >= 3
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    stats = dict(rho=torch.zeros(n, dtype=torch.float64, device=DEV),
+                 xi=torch.zeros(n, dtype=torch.float64, device=DEV),
+                 restart=torch.zeros(n, dtype=torch.uint8, device=DEV))
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st, n, stats=stats)
+    rs = stats["restart"].cpu().numpy().astype(bool)
+    xi = stats["xi"].cpu().numpy()
+    mism = np.nonzero(rs != ref["restart"])[0]
+    first = int(mism[0]) if len(mism) else n
+    exi = np.abs(xi[:first] - ref["xi"][:first]) / prod[:first]
+    d = ora.rmsd_hu(st.x.cpu().numpy().reshape(ora.image_shape(cfg)), ref["x"], synth.roi_mask(cfg),
+                    synth.HU_PER_MU)
+    say("gpu free-running: %d restarts, mismatches at %s, max |xi err| / scale %.2e, RMSD %.2e HU"
+        % (int(rs.sum()), list(mism), exi.max(), d))
+    assert first == n or first in set(marg.tolist())
+    assert exi.max() <= 1e-3
+    assert d <= 0.5
+    st2 = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    stats2 = {k: torch.zeros_like(v) for k, v in stats.items()}
+    forced = gpu(ref["restart"].astype(np.uint8), torch.uint8)
+    L.lalm_iterate(plan, y, w, denom, beta, delta, st2, n, forced_restart=forced, stats=stats2)
+    d2 = ora.rmsd_hu(st2.x.cpu().numpy().reshape(ora.image_shape(cfg)), ref["x"], synth.roi_mask(cfg),
+                     synth.HU_PER_MU)
+    say("gpu replay: RMSD %.2e HU" % d2)
+    assert np.array_equal(stats2["restart"].cpu().numpy().astype(bool), ref["restart"])
+    np.testing.assert_allclose(stats2["rho"].cpu().numpy(), ref["rho"], rtol=1e-12)
+    assert d2 <= 0.5
+
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_cache")
+
+
+@pytest.mark.timeout(600)
+def test_full_size_axial_iterations_against_oracle(L):
+    """The full 512x512x64 axial workload (984 views, 888 x 64 detector,
+    M = 12, continuation, x0 = 0) against the FP64 oracle's own run of it,
+    stored by tests/make_oracle_cache.py: D_L, and after every stored
+    iteration count K (1, 2, 20) the image on the sampled slices (ROI RMS
+    difference <= 0.5 HU), the FP64 cost of the whole volume (relative
+    1e-4) and the restart decisions of every step so far."""
+    path = os.path.join(CACHE, "cone_axial_512x64.npz")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle run: python tests/make_oracle_cache.py cone_axial_512x64 --iters 1 2 20")
+    c = np.load(path)
+    cfg = synth.get_config("cone_axial_512x64")
+    M, beta, delta = int(c["M"]), float(c["beta"]), float(c["delta"])
+    assert M == cfg["M"] and beta == cfg["beta"]
+    ks = sorted(int(k[3:]) for k in c.files if k.startswith("x_k"))
+    assert ks, "the stored run holds no image yet"
+    sl = c["slices"]
+    shape = ora.image_shape(cfg)
+    data = _problem(cfg)
+    plan, y, w, denom = _gpu_problem(L, cfg, M, data)
+    e_dl = rel_l2(denom.reshape(shape)[sl].cpu().numpy(), c["DL"])
+    say("full-size axial: D_L rel %.2e on slices %s; stored K %s" % (e_dl, list(sl), ks))
+    assert e_dl <= 1e-5
+    n = ks[-1] * M
+    st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
+    stats = dict(rho=torch.zeros(n, dtype=torch.float64, device=DEV),
+                 xi=torch.zeros(n, dtype=torch.float64, device=DEV),
+                 restart=torch.zeros(n, dtype=torch.uint8, device=DEV))
+    mask = synth.roi_mask(cfg)[sl]
+    out = torch.zeros(3, dtype=torch.float64, device=DEV)
+    done = 0
+    for K in ks:
+        L.lalm_iterate(plan, y, w, denom, beta, delta, st, K * M - done, stats=stats)
+        done = K * M
+        xg = st.x.reshape(shape)[sl].cpu().numpy()
+        d = ora.rmsd_hu(xg, c["x_k%d" % K], mask, synth.HU_PER_MU)
+        L.lalm_cost_f64(plan, y, w, beta, delta, st.x, out)
+        cg, co = out.cpu().numpy(), c["cost_k%d" % K]
+        nr = min(done, len(c["restart"]))
+        mism = int(np.sum(stats["restart"].cpu().numpy()[:nr].astype(bool) != c["restart"][:nr].astype(bool)))
+        say("  K=%d: RMSD %.2e HU, Psi gpu %.9e oracle %.9e, restart mismatches %d / %d, restarts %d"
+            % (K, d, cg[0], co[0], mism, nr, int(c["restart"][:nr].sum())))
+        assert d <= 0.5
+        assert abs(cg[0] - co[0]) <= 1e-4 * abs(co[0])
 
 
 @pytest.mark.timeout(900)
