@@ -56,6 +56,29 @@ LALM_API lalm_status lalm_unet_loss_grad(lalm_unet *net, const float *params, co
                                          double hu_scale, int32_t batch, float *grad, double *loss_dev,
                                          hipStream_t stream);
 
+/* Layer-by-layer inspection (a measurement aid, not part of the method):
+ * lalm_unet_loss_grad, and a copy of every tensor the kernels store in
+ * bfloat16, converted to FP32 (exact), into the device array capture of at
+ * least lalm_unet_capture_elems(batch, H, W) floats.  Tensors are NHWC
+ * [batch][h][w][C] and follow each other in this order (level 1: H x W,
+ * level 2: H/2 x W/2, level 3: H/4 x W/4; channels in brackets):
+ *   activations  e1a[32] e1b[32] (1), p1[32] e2a[64] e2b[64] (2), p2[64]
+ *                e3a[128] e3b[128] (3), up2[64] d2a[64] d2b[64] (2),
+ *                up1[32] d1a[32] d1b[32] (1);
+ *   output gradients of the layers, after the ReLU mask, as the backward
+ *   pass stores them: dz_d1b dz_d1a dz_up1 [32] (1), dz_d2b dz_d2a dz_up2
+ *                [64] (2), dz_e3b dz_e3a [128] (3), dz_e2b dz_e2a [64] (2),
+ *                dz_e1b dz_e1a [32] (1).
+ * The input of every layer is one of these tensors (or x), so each layer's
+ * kernels can be checked on their own inputs.  Errors as
+ * lalm_unet_loss_grad, and LALM_E_INVALID when capture is null or too
+ * small.  lalm_unet_capture_elems returns 0 for invalid sizes. */
+LALM_API int64_t lalm_unet_capture_elems(int32_t batch, int32_t height, int32_t width);
+LALM_API lalm_status lalm_unet_capture(lalm_unet *net, const float *params, const float *x, const float *target,
+                                       const uint8_t *mask, double in_scale, double hu_scale, int32_t batch,
+                                       float *grad, double *loss_dev, float *capture, int64_t capture_elems,
+                                       hipStream_t stream);
+
 /* Adam step t (1-based, bias-corrected; beta1 0.9, beta2 0.999, eps 1e-8)
  * on FP32 master parameters with moment buffers m, v (device arrays). */
 LALM_API lalm_status lalm_unet_adam(lalm_unet *net, float *params, const float *grad, float *m, float *v,

@@ -835,6 +835,13 @@ __global__ void mask_to_bf16_kernel(const float *g, const bf16 *act, bf16 *dz, l
     *reinterpret_cast<bf16x8 *>(dz + 8 * i) = o;
 }
 
+// stored bfloat16 tensor -> FP32 copy (exact)
+__global__ void bf16_to_f32_kernel(const bf16 *src, float *dst, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
 // head: out = x + sum_c a[p][c] w[c] + b; with a target also the loss
 // partials and dout = 2 s^2 (out - t) mask / n
 __global__ void head_kernel(const float *x, float inv_scale, int nonneg, const bf16 *a, const float *w,
@@ -1035,6 +1042,33 @@ const LayerDef kLayers[] = {
     {"d2b", 0, 64, 64}, {"up1", 1, 64, 32}, {"d1a", 0, 64, 32}, {"d1b", 0, 32, 32}, {"head", 2, 32, 1}};
 constexpr int kNL = 13;
 enum { E1A, E1B, E2A, E2B, E3A, E3B, UP2, D2A, D2B, UP1, D1A, D1B, HEAD };
+
+// Tensors a capture copies out, in this order: name, level (1: H x W,
+// 2: H/2 x W/2, 3: H/4 x W/4) and channels.  Forward activations, then the
+// stored output gradients (after the ReLU mask) in the order the backward
+// pass makes them.
+struct CapDef { const char *name; int level, ch; };
+const CapDef kCap[] = {
+    {"e1a", 1, 32}, {"e1b", 1, 32}, {"p1", 2, 32}, {"e2a", 2, 64}, {"e2b", 2, 64}, {"p2", 3, 64},
+    {"e3a", 3, 128}, {"e3b", 3, 128}, {"up2", 2, 64}, {"d2a", 2, 64}, {"d2b", 2, 64}, {"up1", 1, 32},
+    {"d1a", 1, 32}, {"d1b", 1, 32},
+    {"dz_d1b", 1, 32}, {"dz_d1a", 1, 32}, {"dz_up1", 1, 32}, {"dz_d2b", 2, 64}, {"dz_d2a", 2, 64},
+    {"dz_up2", 2, 64}, {"dz_e3b", 3, 128}, {"dz_e3a", 3, 128}, {"dz_e2b", 2, 64}, {"dz_e2a", 2, 64},
+    {"dz_e1b", 1, 32}, {"dz_e1a", 1, 32}};
+constexpr int kNCap = 26;
+enum { C_DZ_D1B = 14 };
+
+long long cap_elems(int idx, long long P)
+{
+    const int lv = kCap[idx].level;
+    return (lv == 1 ? P : (lv == 2 ? P / 4 : P / 16)) * kCap[idx].ch;
+}
+long long cap_offset(int idx, long long P)
+{
+    long long o = 0;
+    for (int i = 0; i < idx; ++i) o += cap_elems(i, P);
+    return o;
+}
 
 int64_t wcount(const LayerDef &l)
 {
@@ -1367,9 +1401,13 @@ extern "C" lalm_status lalm_unet_forward(lalm_unet *n, const float *params, cons
     return LALM_OK;
 }
 
-extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, const float *x, const float *target,
-                                           const uint8_t *mask, double in_scale, double hu_scale, int32_t batch,
-                                           float *grad, double *loss_dev, hipStream_t st)
+namespace {
+
+// Loss, parameter gradient and, when cap is set, a copy of every stored
+// tensor (FP32, in kCap order; see lalm_unet_capture).
+lalm_status loss_grad_impl(lalm_unet *n, const float *params, const float *x, const float *target,
+                           const uint8_t *mask, double in_scale, double hu_scale, int32_t batch, float *grad,
+                           double *loss_dev, float *cap, hipStream_t st)
 {
     if (!(in_scale > 0.0)) return ufail(LALM_E_INVALID, "lalm_unet_loss_grad: in_scale must be positive");
     if (!n || !params || !x || !target || !mask || !grad || !loss_dev)
@@ -1390,6 +1428,12 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     const long long P = (long long)B * H * W, P2 = P / 4, P4 = P / 16;
     lalm_status s = run_forward(n, params, x, (float)in_scale, B, st);
     if (s != LALM_OK) return s;
+    auto dump = [&](int idx, const bf16 *src) -> hipError_t {
+        if (!cap) return hipSuccess;
+        const long long cnt = cap_elems(idx, P);
+        hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(nblk(cnt)), dim3(256), 0, st, src, cap + cap_offset(idx, P), cnt);
+        return hipGetLastError();
+    };
     const double s2n = hu_scale * hu_scale / (double)(nm * B);
     const unsigned hb = nblk(P);
     hipLaunchKernelGGL(head_kernel, dim3(hb), dim3(256), 0, st, x, (float)(1.0 / in_scale), 0, n->d1b,
@@ -1408,6 +1452,7 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
         hipLaunchKernelGGL(head_bwd_kernel, dim3(nblk(P * 32)), dim3(256), 0, st, n->dout, n->d1b,
                            params + n->woff[HEAD], n->dzA, P);
         UCHK("unet head backward", hipGetLastError());
+        UCHK("capture dz_d1b", dump(C_DZ_D1B, n->dzA));
     }
     bf16 *dz = n->dzA, *dz2 = n->dzB;
     // d1b: dz_d1b in dz
@@ -1416,38 +1461,45 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     UCHK("d1b dgrad", conv_dgrad(n, D1B, dz, n->gA, 32, nullptr, B, H, W, st));
     UCHK("d1a dz", to_dz(n->gA, n->d1a, dz2, P * 32, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_d1a", dump(C_DZ_D1B + 1, dz));
     // d1a (input = concat[up1, e1b])
     UCHK("d1a wgrad", conv_wgrad(n, D1A, dz, n->up1, 32, n->e1b, 32, grad, B, H, W, st));
     UCHK("d1a bgrad", bias_grad(n, dz, 32, P, grad + n->boff[D1A], st));
     UCHK("d1a dgrad", conv_dgrad(n, D1A, dz, n->gA, 32, n->gSkip1, B, H, W, st));
     UCHK("up1 dz", to_dz(n->gA, nullptr, dz2, P * 32, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_up1", dump(C_DZ_D1B + 2, dz));
     // up1: input d2b at (H2, W2), output gradient dz at (H, W)
     UCHK("up1 wgrad", up_wgrad(n, UP1, dz, n->d2b, grad, B, H2, W2, st));
     UCHK("up1 bgrad", bias_grad(n, dz, 32, P, grad + n->boff[UP1], st));
     UCHK("up1 dgrad", up_dgrad(n, UP1, dz, n->gA, B, H2, W2, st));
     UCHK("d2b dz", to_dz(n->gA, n->d2b, dz2, P2 * 64, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_d2b", dump(C_DZ_D1B + 3, dz));
     UCHK("d2b wgrad", conv_wgrad(n, D2B, dz, n->d2a, 64, nullptr, 0, grad, B, H2, W2, st));
     UCHK("d2b bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[D2B], st));
     UCHK("d2b dgrad", conv_dgrad(n, D2B, dz, n->gA, 64, nullptr, B, H2, W2, st));
     UCHK("d2a dz", to_dz(n->gA, n->d2a, dz2, P2 * 64, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_d2a", dump(C_DZ_D1B + 4, dz));
     UCHK("d2a wgrad", conv_wgrad(n, D2A, dz, n->up2, 64, n->e2b, 64, grad, B, H2, W2, st));
     UCHK("d2a bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[D2A], st));
     UCHK("d2a dgrad", conv_dgrad(n, D2A, dz, n->gA, 64, n->gSkip2, B, H2, W2, st));
     UCHK("up2 dz", to_dz(n->gA, nullptr, dz2, P2 * 64, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_up2", dump(C_DZ_D1B + 5, dz));
     UCHK("up2 wgrad", up_wgrad(n, UP2, dz, n->e3b, grad, B, H4, W4, st));
     UCHK("up2 bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[UP2], st));
     UCHK("up2 dgrad", up_dgrad(n, UP2, dz, n->gA, B, H4, W4, st));
     UCHK("e3b dz", to_dz(n->gA, n->e3b, dz2, P4 * 128, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_e3b", dump(C_DZ_D1B + 6, dz));
     UCHK("e3b wgrad", conv_wgrad(n, E3B, dz, n->e3a, 128, nullptr, 0, grad, B, H4, W4, st));
     UCHK("e3b bgrad", bias_grad(n, dz, 128, P4, grad + n->boff[E3B], st));
     UCHK("e3b dgrad", conv_dgrad(n, E3B, dz, n->gA, 128, nullptr, B, H4, W4, st));
     UCHK("e3a dz", to_dz(n->gA, n->e3a, dz2, P4 * 128, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_e3a", dump(C_DZ_D1B + 7, dz));
     UCHK("e3a wgrad", conv_wgrad(n, E3A, dz, n->p2, 64, nullptr, 0, grad, B, H4, W4, st));
     UCHK("e3a bgrad", bias_grad(n, dz, 128, P4, grad + n->boff[E3A], st));
     UCHK("e3a dgrad", conv_dgrad(n, E3A, dz, n->gA, 64, nullptr, B, H4, W4, st));
@@ -1456,11 +1508,13 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     UCHK("pool2 backward", hipGetLastError());
     UCHK("e2b dz", to_dz(n->gSkip2, n->e2b, dz2, P2 * 64, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_e2b", dump(C_DZ_D1B + 8, dz));
     UCHK("e2b wgrad", conv_wgrad(n, E2B, dz, n->e2a, 64, nullptr, 0, grad, B, H2, W2, st));
     UCHK("e2b bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[E2B], st));
     UCHK("e2b dgrad", conv_dgrad(n, E2B, dz, n->gA, 64, nullptr, B, H2, W2, st));
     UCHK("e2a dz", to_dz(n->gA, n->e2a, dz2, P2 * 64, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_e2a", dump(C_DZ_D1B + 9, dz));
     UCHK("e2a wgrad", conv_wgrad(n, E2A, dz, n->p1, 32, nullptr, 0, grad, B, H2, W2, st));
     UCHK("e2a bgrad", bias_grad(n, dz, 64, P2, grad + n->boff[E2A], st));
     UCHK("e2a dgrad", conv_dgrad(n, E2A, dz, n->gA, 32, nullptr, B, H2, W2, st));
@@ -1468,11 +1522,13 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
     UCHK("pool1 backward", hipGetLastError());
     UCHK("e1b dz", to_dz(n->gSkip1, n->e1b, dz2, P * 32, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_e1b", dump(C_DZ_D1B + 10, dz));
     UCHK("e1b wgrad", conv_wgrad(n, E1B, dz, n->e1a, 32, nullptr, 0, grad, B, H, W, st));
     UCHK("e1b bgrad", bias_grad(n, dz, 32, P, grad + n->boff[E1B], st));
     UCHK("e1b dgrad", conv_dgrad(n, E1B, dz, n->gA, 32, nullptr, B, H, W, st));
     UCHK("e1a dz", to_dz(n->gA, n->e1a, dz2, P * 32, st));
     std::swap(dz, dz2);
+    UCHK("capture dz_e1a", dump(C_DZ_D1B + 11, dz));
     {
         // 1024 pixels per block: enough blocks to fill the chip at every batch size
         const int chunk = 1024, ns = (int)((P + chunk - 1) / chunk);
@@ -1484,7 +1540,40 @@ extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, co
                            grad + n->boff[E1A]);
         UCHK("e1a wgrad", hipGetLastError());
     }
+    if (cap) {
+        const bf16 *acts[14] = {n->e1a, n->e1b, n->p1, n->e2a, n->e2b, n->p2, n->e3a,
+                                n->e3b, n->up2, n->d2a, n->d2b, n->up1, n->d1a, n->d1b};
+        for (int i = 0; i < 14; ++i) UCHK("capture activations", dump(i, acts[i]));
+    }
     return LALM_OK;
+}
+
+}  // namespace
+
+extern "C" lalm_status lalm_unet_loss_grad(lalm_unet *n, const float *params, const float *x, const float *target,
+                                           const uint8_t *mask, double in_scale, double hu_scale, int32_t batch,
+                                           float *grad, double *loss_dev, hipStream_t st)
+{
+    return loss_grad_impl(n, params, x, target, mask, in_scale, hu_scale, batch, grad, loss_dev, nullptr, st);
+}
+
+extern "C" int64_t lalm_unet_capture_elems(int32_t batch, int32_t height, int32_t width)
+{
+    if (batch < 1 || height < 4 || width < 4 || height % 4 || width % 4) return 0;
+    const long long P = (long long)batch * height * width;
+    return cap_offset(kNCap, P);
+}
+
+extern "C" lalm_status lalm_unet_capture(lalm_unet *n, const float *params, const float *x, const float *target,
+                                         const uint8_t *mask, double in_scale, double hu_scale, int32_t batch,
+                                         float *grad, double *loss_dev, float *capture, int64_t capture_elems,
+                                         hipStream_t st)
+{
+    if (!n || !capture) return ufail(LALM_E_INVALID, "lalm_unet_capture: null argument");
+    if (batch < 1 || batch > n->Bmax) return ufail(LALM_E_INVALID, "lalm_unet_capture: batch out of range");
+    if (capture_elems < lalm_unet_capture_elems(batch, n->H, n->W))
+        return ufail(LALM_E_INVALID, "lalm_unet_capture: capture buffer too small");
+    return loss_grad_impl(n, params, x, target, mask, in_scale, hu_scale, batch, grad, loss_dev, capture, st);
 }
 
 extern "C" lalm_status lalm_unet_adam(lalm_unet *n, float *params, const float *grad, float *m, float *v, int64_t t,

@@ -24,7 +24,8 @@ EXPORTS = ("lalm_last_error", "lalm_version", "lalm_plan_geometry", "lalm_plan_i
            "lalm_sqs_denom", "lalm_fbp", "lalm_iterate", "lalm_cost_f64", "lalm_dot_f64",
            "lalm_roi_rmsd_f64", "lalm_profile_begin", "lalm_profile_read",
            "lalm_profile_end", "lalm_unet_param_count", "lalm_unet_create",
-           "lalm_unet_destroy", "lalm_unet_forward", "lalm_unet_loss_grad", "lalm_unet_adam")
+           "lalm_unet_destroy", "lalm_unet_forward", "lalm_unet_loss_grad", "lalm_unet_adam",
+           "lalm_unet_capture_elems", "lalm_unet_capture")
 
 
 class LalmError(RuntimeError):
@@ -97,6 +98,8 @@ def _load():
         "lalm_unet_forward": ([P, P, P, P, I32, F64, I32, P], I32),
         "lalm_unet_loss_grad": ([P, P, P, P, P, F64, F64, I32, P, P, P], I32),
         "lalm_unet_adam": ([P, P, P, P, P, I64, F64, P], I32),
+        "lalm_unet_capture_elems": ([I32, I32, I32], I64),
+        "lalm_unet_capture": ([P, P, P, P, P, F64, F64, I32, P, P, P, I64, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -408,3 +411,38 @@ def lalm_unet_adam(net, params, grad, m, v, t, lr, stream=None):
     _check(_lib.lalm_unet_adam(net.handle, _dev(params, "params", numel=P), _dev(grad, "grad", numel=P),
                                _dev(m, "m", numel=P), _dev(v, "v", numel=P), int(t), float(lr),
                                _stream(stream)))
+
+
+# tensors of lalm_unet_capture, in order: (name, level, channels)
+UNET_CAPTURE = (("e1a", 1, 32), ("e1b", 1, 32), ("p1", 2, 32), ("e2a", 2, 64), ("e2b", 2, 64), ("p2", 3, 64),
+                ("e3a", 3, 128), ("e3b", 3, 128), ("up2", 2, 64), ("d2a", 2, 64), ("d2b", 2, 64),
+                ("up1", 1, 32), ("d1a", 1, 32), ("d1b", 1, 32),
+                ("dz_d1b", 1, 32), ("dz_d1a", 1, 32), ("dz_up1", 1, 32), ("dz_d2b", 2, 64),
+                ("dz_d2a", 2, 64), ("dz_up2", 2, 64), ("dz_e3b", 3, 128), ("dz_e3a", 3, 128),
+                ("dz_e2b", 2, 64), ("dz_e2a", 2, 64), ("dz_e1b", 1, 32), ("dz_e1a", 1, 32))
+
+
+def lalm_unet_capture_elems(batch, height, width):
+    return int(_lib.lalm_unet_capture_elems(int(batch), int(height), int(width)))
+
+
+def lalm_unet_capture(net, params, x, target, mask, hu_scale, batch, grad, loss, capture, in_scale=1.0,
+                      stream=None):
+    """lalm_unet_loss_grad plus a copy of every stored tensor into ``capture``
+    (float32 GPU tensor); returns a dict name -> view [batch, h, w, C]."""
+    n = int(batch) * net.height * net.width
+    P = lalm_unet_param_count()
+    need = lalm_unet_capture_elems(batch, net.height, net.width)
+    _check(_lib.lalm_unet_capture(net.handle, _dev(params, "params", numel=P), _dev(x, "x", numel=n),
+                                  _dev(target, "target", numel=n),
+                                  _dev(mask, "mask", dtype="uint8", numel=net.height * net.width),
+                                  float(in_scale), float(hu_scale), int(batch), _dev(grad, "grad", numel=P),
+                                  _dev(loss, "loss", dtype="float64", numel=1),
+                                  _dev(capture, "capture", numel=need), int(capture.numel()), _stream(stream)))
+    out, o = {}, 0
+    for name, lv, ch in UNET_CAPTURE:
+        h, w = net.height >> (lv - 1), net.width >> (lv - 1)
+        cnt = int(batch) * h * w * ch
+        out[name] = capture[o:o + cnt].view(int(batch), h, w, ch)
+        o += cnt
+    return out

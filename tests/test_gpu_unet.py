@@ -124,3 +124,164 @@ def test_adam_and_training_decreases_loss(L):
         L.lalm_unet_adam(net, params, grad, m, v, k, 1e-3)
     say("  training losses", losses[0], losses[-1])
     assert losses[-1] < 0.5 * losses[0]
+
+
+# ------------------------------------------------------- layer by layer, 512^2
+
+U_EPS = 2.0 ** -24          # FP32 unit roundoff
+BF16_HALF = 2.0 ** -8       # bfloat16 half-step, relative bound (at a binade's low end)
+
+
+def _check_stored(name, got, v, delta):
+    """A tensor the kernels store in bfloat16 against the exact (FP64) value
+    v of the same layer on the same inputs.  The kernels round their FP32
+    result to bfloat16; that result lies within delta (the FP32 accumulation
+    bound) of v, so |got - v| <= 2^-8 (|v| + delta) + delta must hold for
+    every element, and all but a few near-tie elements must equal the
+    correctly rounded bfloat16 of v (at least 99 %)."""
+    err = np.abs(got - v)
+    bound = BF16_HALF * (np.abs(v) + delta) + delta
+    exact = float(np.mean(got == U.bf16_round(v)))
+    vmax = float(np.abs(v).max())
+    worst = float(np.max(err - bound))
+    say("  %-7s max |err| / max|v| %.2e, bit-exact %.5f, worst err - bound %.2e (max|v| %.3e)"
+        % (name, err.max() / max(vmax, 1e-300), exact, worst, vmax))
+    assert np.all(err <= bound), name
+    assert exact >= 0.99, name
+    assert vmax > 0.0, name
+
+
+def _check_wgrad(name, got, want):
+    """FP32 parameter gradients against the FP64 sums over the same inputs:
+    element-wise <= 1e-3 x max |want|."""
+    e = float(np.abs(got - want).max() / np.abs(want).max())
+    say("  %-7s weight/bias gradient max |err| / max %.2e, rel L2 %.2e" % (name, e, rel_l2(got, want)))
+    assert e <= 1e-3, name
+
+
+@pytest.mark.timeout(900)
+def test_layer_by_layer_parity_512(L):
+    """Every layer of the network at the warm start's size (batch 2 of 512 x
+    512 images, the committed trained weights) on its own inputs: each
+    layer's input is the tensor the GPU stored for it (captured through the
+    C ABI), the FP64 oracle layer computes from exactly those bfloat16
+    values, and the GPU's stored output (activation or output gradient) and
+    its FP32 weight gradients are compared with the oracle's.  This
+    separates each kernel's error from bfloat16 rounding flips carried over
+    from earlier layers."""
+    import os
+    B, H, W = 2, 512, 512
+    in_scale, hu = 50.0, 50000.0
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_1402_4381_amd", "weights", "unet_fan2d_512.npy")
+    th = np.load(wpath).astype(np.float64)
+    rng = np.random.default_rng(31)
+    yy, xx = np.mgrid[0:H, 0:W]
+    r2 = ((yy - H / 2 + 0.5) ** 2 + (xx - W / 2 + 0.5) ** 2) / (0.45 * H) ** 2
+    body = np.where(r2 < 1.0, 0.02, 0.0)
+    x = np.stack([body * (1.0 + 0.1 * np.sin(0.05 * (k + 1) * xx)) + rng.normal(0, 0.002, (H, W))
+                  for k in range(B)]).astype(np.float32)
+    t = (x + rng.normal(0, 4e-4, x.shape)).astype(np.float32)
+    mask = (r2 < 0.8).astype(np.uint8)
+    net = L.lalm_unet_create(B, H, W)
+    P = L.lalm_unet_param_count()
+    grad = torch.zeros(P, device=DEV)
+    lg = torch.zeros(1, dtype=torch.float64, device=DEV)
+    cap = torch.empty(L.lalm_unet_capture_elems(B, H, W), device=DEV)
+    T = L.lalm_unet_capture(net, g32(th), g32(x).reshape(-1), g32(t).reshape(-1),
+                            g32(mask, torch.uint8).reshape(-1), hu, B, grad, lg, cap, in_scale=in_scale)
+    T = {k: v.cpu().numpy().astype(np.float64) for k, v in T.items()}
+    del cap
+    gg = grad.cpu().numpy().astype(np.float64)
+    torch.cuda.empty_cache()
+    Pw = {k: (U.bf16_round(w), b) for k, (w, b) in U.unpack(th).items()}
+    Pa = {k: (np.abs(w), np.abs(b)) for k, (w, b) in Pw.items()}
+    goff, o = {}, 0
+    for name, ws, bs in U.param_shapes():
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        goff[name] = (gg[o:o + nw].reshape(ws), gg[o + nw:o + nw + nb])
+        o += nw + nb
+    relu = lambda z: np.maximum(z, 0.0)
+    u = U.bf16_round(in_scale * x.astype(np.float64)[..., None])
+
+    # forward: (layer, input, K = products per output)
+    say("forward layers")
+    cat2 = np.concatenate([T["up2"], T["e2b"]], axis=-1)
+    cat1 = np.concatenate([T["up1"], T["e1b"]], axis=-1)
+    conv_in = {"e1a": u, "e1b": T["e1a"], "e2a": T["p1"], "e2b": T["e2a"], "e3a": T["p2"], "e3b": T["e3a"],
+               "d2a": cat2, "d2b": T["d2a"], "d1a": cat1, "d1b": T["d1a"]}
+    for name, xin in conv_in.items():
+        v = relu(U.conv3x3(xin, *Pw[name]))
+        A = U.conv3x3(np.abs(xin), *Pa[name])
+        _check_stored(name, T[name], v, 9 * xin.shape[-1] * U_EPS * A)
+    assert np.array_equal(T["p1"], U.maxpool2(T["e1b"])) and np.array_equal(T["p2"], U.maxpool2(T["e2b"]))
+    for name, xin in (("up2", T["e3b"]), ("up1", T["d2b"])):
+        v = U.upconv2(xin, *Pw[name])
+        A = U.upconv2(np.abs(xin), *Pa[name])
+        _check_stored(name, T[name], v, xin.shape[-1] * U_EPS * A)
+
+    # head: the loss gradient w.r.t. the head output and dz of d1b
+    say("backward layers")
+    hw, hb = Pw["head"]
+    x64, t64 = x.astype(np.float64), t.astype(np.float64)
+    m = np.broadcast_to(mask.astype(bool), x.shape)
+    n_m = float(m.sum())
+    acc = T["d1b"] @ hw + hb[0]
+    o64 = x64 + acc / in_scale
+    dout = 2.0 * hu ** 2 * (o64 - t64) * m / n_m / in_scale
+    # FP32: 32 products and the bias summed, scaled and added to x, then
+    # the difference to the target (FP64) scaled and rounded
+    S = np.abs(T["d1b"]) @ np.abs(hw) + abs(hb[0])
+    do_err = 2.0 * hu ** 2 * m / n_m / in_scale * (2 * U_EPS * np.abs(x64) + 34 * U_EPS * S / in_scale)
+    do_err = do_err + 2 * U_EPS * np.abs(dout)
+    d1b_on = T["d1b"] > 0
+    v = d1b_on * dout[..., None] * hw
+    _check_stored("dz_d1b", T["dz_d1b"], v, d1b_on * do_err[..., None] * np.abs(hw) + U_EPS * np.abs(v))
+    _check_wgrad("head", np.concatenate([goff["head"][0], goff["head"][1]]),
+                 np.concatenate([np.einsum("bhwc,bhw->c", T["d1b"], dout), [dout.sum()]]))
+
+    def dgrad(name, xin, dz):
+        """FP64 input gradient of a 3x3 layer and its absolute-sum bound."""
+        dx, dw, db = U.conv3x3_backward(xin, Pw[name][0], dz)
+        ax = U.conv3x3_backward(xin, Pa[name][0], np.abs(dz))[0]
+        _check_wgrad(name, np.concatenate([goff[name][0].ravel(), goff[name][1]]),
+                     np.concatenate([dw.ravel(), db]))
+        return dx, 9 * dz.shape[-1] * U_EPS * ax
+
+    def dgrad_up(name, xin, dz):
+        dx, dw, db = U.upconv2_backward(xin, Pw[name][0], dz)
+        ax = U.upconv2_backward(xin, Pa[name][0], np.abs(dz))[0]
+        _check_wgrad(name, np.concatenate([goff[name][0].ravel(), goff[name][1]]),
+                     np.concatenate([dw.ravel(), db]))
+        return dx, 4 * dz.shape[-1] * U_EPS * ax
+
+    on = lambda a: (a > 0).astype(np.float64)
+    dx, e = dgrad("d1b", T["d1a"], T["dz_d1b"])
+    _check_stored("dz_d1a", T["dz_d1a"], on(T["d1a"]) * dx, on(T["d1a"]) * e)
+    dx, e = dgrad("d1a", cat1, T["dz_d1a"])
+    _check_stored("dz_up1", T["dz_up1"], dx[..., :32], e[..., :32])
+    skip1, eskip1 = dx[..., 32:], e[..., 32:]
+    dx, e = dgrad_up("up1", T["d2b"], T["dz_up1"])
+    _check_stored("dz_d2b", T["dz_d2b"], on(T["d2b"]) * dx, on(T["d2b"]) * e)
+    dx, e = dgrad("d2b", T["d2a"], T["dz_d2b"])
+    _check_stored("dz_d2a", T["dz_d2a"], on(T["d2a"]) * dx, on(T["d2a"]) * e)
+    dx, e = dgrad("d2a", cat2, T["dz_d2a"])
+    _check_stored("dz_up2", T["dz_up2"], dx[..., :64], e[..., :64])
+    skip2, eskip2 = dx[..., 64:], e[..., 64:]
+    dx, e = dgrad_up("up2", T["e3b"], T["dz_up2"])
+    _check_stored("dz_e3b", T["dz_e3b"], on(T["e3b"]) * dx, on(T["e3b"]) * e)
+    dx, e = dgrad("e3b", T["e3a"], T["dz_e3b"])
+    _check_stored("dz_e3a", T["dz_e3a"], on(T["e3a"]) * dx, on(T["e3a"]) * e)
+    dx, e = dgrad("e3a", T["p2"], T["dz_e3a"])
+    s = U.maxpool2_backward(T["e2b"], dx) + skip2
+    es = U.maxpool2_backward(T["e2b"], e) + eskip2 + U_EPS * np.abs(s)
+    _check_stored("dz_e2b", T["dz_e2b"], on(T["e2b"]) * s, on(T["e2b"]) * es)
+    dx, e = dgrad("e2b", T["e2a"], T["dz_e2b"])
+    _check_stored("dz_e2a", T["dz_e2a"], on(T["e2a"]) * dx, on(T["e2a"]) * e)
+    dx, e = dgrad("e2a", T["p1"], T["dz_e2a"])
+    s = U.maxpool2_backward(T["e1b"], dx) + skip1
+    es = U.maxpool2_backward(T["e1b"], e) + eskip1 + U_EPS * np.abs(s)
+    _check_stored("dz_e1b", T["dz_e1b"], on(T["e1b"]) * s, on(T["e1b"]) * es)
+    dx, e = dgrad("e1b", T["e1a"], T["dz_e1b"])
+    _check_stored("dz_e1a", T["dz_e1a"], on(T["e1a"]) * dx, on(T["e1a"]) * e)
+    dgrad("e1a", u, T["dz_e1a"])
