@@ -691,3 +691,86 @@ def fbp_fan(cfg, sino):
             val[ok] += wgt[ok] * Q[v, bb[ok]]
         f += dbeta * val / (dx_ * dx_ + dy_ * dy_)
     return f[None]
+
+
+def _fan_ramp_kernel(nb, dg):
+    """The equiangular fan-beam Ram-Lak kernel of :func:`fbp_fan` on the
+    offsets n = -(nb-1) .. nb-1: g(n dg) = 1/2 (n dg / sin(n dg))^2 h(n dg)."""
+    n = np.arange(-(nb - 1), nb)
+    h = np.zeros(n.shape)
+    h[n == 0] = 1.0 / (4.0 * dg * dg)
+    odd = (n % 2) != 0
+    h[odd] = -1.0 / (n[odd] * np.pi * dg) ** 2
+    ratio = np.ones(n.shape)
+    nz = n != 0
+    ratio[nz] = (n[nz] * dg) / np.sin(n[nz] * dg)
+    return 0.5 * ratio * ratio * h
+
+
+def fbp_cone_axial(cfg, sino, voxels=None):
+    """Initial image for the axial cone beam: the FDK reconstruction
+    (Feldkamp, Davis & Kress) for the cylindrical (arc) detector over a full
+    turn; the paper's experiments start from an FBP image (figure captions)
+    and give no formula, so this is the textbook reading:
+
+    1. cosine weights of the fan and the cone angle,
+       q = p D cos(gamma) dsd / sqrt(dsd^2 + v_r^2)  (D = dso, v_r the row
+       height at the detector, which is a cylinder of radius dsd about the
+       source);
+    2. every detector row filtered along the channels with the fan-beam
+       kernel of :func:`fbp_fan`, Q = dgamma (q * g);
+    3. f(P) = dbeta sum_views Q(gamma'(P), v'(P)) / L(P)^2, L the in-plane
+       distance from the source to P, gamma'(P) the fan angle of P and
+       v'(P) = (z_P - z_s) dsd / L the height at which the ray through P
+       meets the detector; Q interpolated bilinearly in (channel, row), zero
+       off the detector.
+
+    With one detector row at v = 0 and one slice it is :func:`fbp_fan`.
+
+    sino: natural-order [n_views][n_rows][n_bins] line integrals.  Returns
+    the image [nz][ny][nx], or, with voxels (a list of (k, j, i)), the
+    values at those voxels only."""
+    if cfg["kind"] != 1 or cfg["n_views"] != cfg["n_views_per_turn"]:
+        raise ValueError("fbp_cone_axial: axial cone beam over one full turn only")
+    nb, nr, nv = cfg["n_bins"], cfg["n_rows"], cfg["n_views"]
+    p = np.asarray(sino, dtype=np.float64).reshape(nv, nr, nb)
+    dg = cfg["ds"] / cfg["dsd"]
+    D, dsd = cfg["dso"], cfg["dsd"]
+    gam = (np.arange(nb) - (nb - 1) / 2.0 - cfg["channel_offset"]) * dg
+    vr = (np.arange(nr) - (nr - 1) / 2.0) * cfg["dt"]
+    q = p * (D * np.cos(gam))[None, None, :] * (dsd / np.sqrt(dsd * dsd + vr * vr))[None, :, None]
+    g = _fan_ramp_kernel(nb, dg)
+    # Toeplitz matrix of the convolution restricted to the detector: T[k, b] = g(b - k)
+    kk, bb = np.meshgrid(np.arange(nb), np.arange(nb), indexing="ij")
+    T = g[(bb - kk) + (nb - 1)]
+    Q = dg * (q.reshape(-1, nb) @ T).reshape(nv, nr, nb)
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    if voxels is None:
+        K, J, I = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    else:
+        vox = np.asarray(voxels, dtype=np.int64).reshape(-1, 3)
+        K, J, I = vox[:, 0], vox[:, 1], vox[:, 2]
+    PX = (I - (nx - 1) / 2.0) * cfg["dx"]
+    PY = (J - (ny - 1) / 2.0) * cfg["dy"]
+    PZ = (K - (nz - 1) / 2.0) * cfg["dz"]
+    dbeta = 2.0 * np.pi / cfg["n_views_per_turn"]
+    f = np.zeros(PX.shape)
+    for v in range(nv):
+        beta = cfg["start_angle"] + 2.0 * np.pi * v / cfg["n_views_per_turn"]
+        sx, sy = D * np.cos(beta), D * np.sin(beta)
+        dx_, dy_ = PX - sx, PY - sy
+        along = -(dx_ * np.cos(beta) + dy_ * np.sin(beta))
+        perp = dx_ * np.sin(beta) - dy_ * np.cos(beta)
+        L2 = dx_ * dx_ + dy_ * dy_
+        bc = np.arctan2(perp, along) / dg + (nb - 1) / 2.0 + cfg["channel_offset"]
+        rc = PZ * dsd / np.sqrt(L2) / cfg["dt"] + (nr - 1) / 2.0
+        b0 = np.floor(bc).astype(np.int64)
+        r0 = np.floor(rc).astype(np.int64)
+        tb, tr = bc - b0, rc - r0
+        val = np.zeros(PX.shape)
+        for rr, wr in ((r0, 1.0 - tr), (r0 + 1, tr)):
+            for b_, wb in ((b0, 1.0 - tb), (b0 + 1, tb)):
+                ok = (b_ >= 0) & (b_ < nb) & (rr >= 0) & (rr < nr)
+                val[ok] += (wr * wb)[ok] * Q[v, rr[ok], b_[ok]]
+        f += dbeta * val / L2
+    return f
