@@ -165,12 +165,23 @@ LALM_API lalm_status lalm_backproject_subset(lalm_plan *plan, int32_t m, const f
 LALM_API lalm_status lalm_sqs_denom(lalm_plan *plan, const float *w_full, float *denom, hipStream_t stream);
 
 /* Initial image by filtered back-projection (the paper's experiments start
- * from an FBP image; figure captions): textbook equiangular fan-beam FBP of
- * the line integrals y_full (device, subset-major like lalm_iterate's y;
- * rays with zero counts carry y = 0) into x_out (device [ny][nx]): cosine
- * weighting, the fan-beam Ram-Lak kernel, 1/L^2-weighted back-projection
- * with linear interpolation in channel, FP32.  2D fan beam over one full
- * turn only; LALM_E_INVALID otherwise or for more than 4096 channels. */
+ * from an FBP image; figure captions), over one full turn, FP32, into x_out
+ * (device image [z][y][x]) from the line integrals y_full (device,
+ * subset-major like lalm_iterate's y; rays with zero counts carry y = 0).
+ * The paper gives no formula; these are the textbook reconstructions for
+ * the arc (equiangular, cylindrical) detector:
+ *   2D fan beam   cosine weighting D cos(gamma), the fan-beam Ram-Lak
+ *                 kernel along the channels, 1/L^2-weighted back-projection
+ *                 with linear interpolation in channel;
+ *   axial cone    FDK (Feldkamp, Davis & Kress): the weight also carries the
+ *                 row's cone angle dsd / sqrt(dsd^2 + v_r^2), each detector
+ *                 row is filtered on its own, and a voxel at height z reads
+ *                 the row height z dsd / L (L: in-plane distance from the
+ *                 source), bilinear in (channel, row), weight 1/L^2.
+ * The helical cone beam has no such one-pass reconstruction (its rays cover
+ * each slice from a different set of angles) and is rejected.
+ * Errors: LALM_E_INVALID for helical plans, scans that are not one full
+ * turn, or more than 4096 channels. */
 LALM_API lalm_status lalm_fbp(lalm_plan *plan, const float *y_full, float *x_out, hipStream_t stream);
 
 /* The PWLS problem of Sec. IV: data, weights, SQS denominator, and the

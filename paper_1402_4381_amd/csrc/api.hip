@@ -106,8 +106,8 @@ extern "C" lalm_status lalm_sqs_denom(lalm_plan *p, const float *w_full, float *
 extern "C" lalm_status lalm_fbp(lalm_plan *p, const float *y_full, float *x_out, hipStream_t st)
 {
     if (!p || !y_full || !x_out) return fail(LALM_E_INVALID, "lalm_fbp: null argument");
-    if (p->is3d || p->g.n_views != p->g.n_views_per_turn)
-        return fail(LALM_E_INVALID, "lalm_fbp: 2D fan beam over one full turn only");
+    if (p->g.kind == LALM_CONE_HELICAL || p->g.n_views != p->g.n_views_per_turn || !p->d_fbpq)
+        return fail(LALM_E_INVALID, "lalm_fbp: 2D fan beam or axial cone beam over one full turn only");
     if (p->nb > fbp_max_bins()) return fail(LALM_E_INVALID, "lalm_fbp: too many channels");
     HIPCHK("fbp", launch_fbp(p, y_full, x_out, st));
     return LALM_OK;

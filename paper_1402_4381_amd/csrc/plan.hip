@@ -329,8 +329,10 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(dev_alloc(&p->d_part, nvox));
     chk(dev_alloc(&p->d_part2, nvox));
     chk(dev_alloc(&p->d_v, nvox));
+    // filtered sinogram of the initial image (fan-beam FBP, axial FDK)
+    if (!is3d || (g.kind == LALM_CONE_AXIAL && g.n_views == g.n_views_per_turn))
+        chk(dev_alloc(&p->d_fbpq, (size_t)p->nv * nr * p->nb));
     if (!is3d) {
-        chk(dev_alloc(&p->d_fbpq, (size_t)p->nv * p->nb));
         chk(dev_alloc(&p->d_xt1, (size_t)g.nx * K.slabT));
         chk(dev_alloc(&p->d_xn1, (size_t)g.ny * K.slabN));
         chk(dev_alloc(&p->d_xc, 4 * nvox));
