@@ -6,9 +6,12 @@ every stored tensor to bfloat16, so an element whose FP32 and FP64 values
 straddle a bfloat16 rounding boundary differs by one bfloat16 step (2^-8
 relative).  Such flips are rare (~FP32 error / bf16 step ~ 1e-3 of the
 elements) and propagate through at most 26 layers of the forward and
-backward passes, hence: network correction (output - input) relative L2
-<= 1e-2; loss relative 1e-3; per-layer gradients relative L2 <= 2e-2
-(the first layers see the most propagated flips); Adam step 1e-6.
+backward passes.  The layer-by-layer test below shows each kernel exact up
+to such near-ties on its own inputs; the end-to-end checks allow what the
+propagated flips give (measured: correction 5e-4, gradients up to 7.4e-3 on
+the smallest image): network correction (output - input) relative L2
+<= 2e-3; loss relative 1e-3; per-layer gradients relative L2 <= 1e-2;
+Adam step 1e-6.
 """
 import numpy as np
 import pytest
@@ -57,7 +60,7 @@ def test_forward_parity(L, B, H, W):
     got = out.cpu().numpy().reshape(B, H, W).astype(np.float64)
     e = rel_l2(got - x, ref - x)
     say("  correction rel L2 %.2e" % e)
-    assert e <= 1e-2
+    assert e <= 2e-3
 
 
 @pytest.mark.parametrize("B,H,W", [(2, 16, 16), (1, 32, 24)])
@@ -86,7 +89,7 @@ def test_loss_gradient_parity(L, B, H, W):
         ew = rel_l2(gg[o:o + nw], g[o:o + nw])
         eb = rel_l2(gg[o + nw:o + nw + nb], g[o + nw:o + nw + nb])
         say("  %-4s dW rel %.2e  db rel %.2e" % (name, ew, eb))
-        assert ew <= 2e-2 and eb <= 2e-2
+        assert ew <= 1e-2 and eb <= 1e-2
         o += nw + nb
     # deterministic
     grad2 = torch.zeros(P, device=DEV)
