@@ -105,13 +105,17 @@ class Problem:
 
 
 class Pipeline:
-    def __init__(self, cfg, dev="cuda:0"):
+    def __init__(self, cfg, dev="cuda:0", n_inner=1):
         import torch
         import synth
         from paper_1402_4381_amd import lalm
         self.torch, self.synth, self.lalm = torch, synth, lalm
         self.cfg, self.dev = cfg, dev
         self.M = cfg["M"]
+        # inner FISTA iterations per subset step of every OS-LALM run of the
+        # pipeline (pairs, plain and warm-started evaluation runs); x* always
+        # uses the one-subset method with n = 1
+        self.n_inner = int(n_inner)
         self.plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), self.M)
         self.beta = cfg["beta"]
         self.delta = synth.configs.delta_mu(cfg)
@@ -129,7 +133,7 @@ class Pipeline:
 
     def iterate(self, prob, state, n_iters):
         self.lalm.lalm_iterate(self.plan, prob.y, prob.w, prob.denom, self.beta, self.delta, state,
-                               n_iters * self.M)
+                               n_iters * self.M, n_inner=self.n_inner)
 
     def rmsd_hu(self, a, b):
         self.lalm.lalm_roi_rmsd_f64(self.plan, a, b, self.radius, self._r)
@@ -520,6 +524,8 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=14)
     ap.add_argument("--weights", default=WEIGHTS, help="weights file to write (train) or read (eval only)")
     ap.add_argument("--eval-only", action="store_true")
+    ap.add_argument("--n-inner", type=int, default=1,
+                    help="inner FISTA iterations per subset step of the plain and warm-started runs")
     ap.add_argument("--volume", default=None,
                     help="3D workload: per-slice warm start with the committed weights (no training)")
     ap.add_argument("--out", default=None, help="JSON summary path")
@@ -546,9 +552,9 @@ def main(argv=None):
         # CPU workers are forked before the GPU is touched
         pool = mp.get_context("fork").Pool(args.workers, initializer=_worker_init, initargs=(cfg,))
 
-    pipe = Pipeline(cfg)
+    pipe = Pipeline(cfg, n_inner=args.n_inner)
     torch = pipe.torch
-    report = dict(workload=args.workload, warmstart=ws)
+    report = dict(workload=args.workload, warmstart=ws, n_inner=args.n_inner)
     if args.eval_only:
         params = torch.as_tensor(np.load(args.weights), device=pipe.dev).contiguous()
     else:
