@@ -19,6 +19,13 @@
  *   - Images are float32 [z][y][x], x fastest.  Voxel centres are
  *     X_i = (i - (nx-1)/2) dx (same for y, z): the image centre is the
  *     isocentre.
+ *   - A plan holds a batch of B images of the same geometry (B = 1 for a
+ *     single reconstruction).  Every image argument then holds B images one
+ *     after the other ([batch][z][y][x]), every sinogram argument B
+ *     sinograms ([batch][sinogram]), every subset argument B subset arrays
+ *     ([batch][rays of the subset]); each kernel launch covers all B, and the
+ *     B reconstructions are independent (each has its own data, weights,
+ *     D_L and continuation state).
  *   - Sinograms are float32 and subset-major: views are grouped by subset
  *     (subset m holds the views v with v mod M == m, in increasing order);
  *     lalm_plan_info returns the view of every slot and the ray offset of
@@ -94,19 +101,22 @@ typedef struct lalm_plan lalm_plan;
 /*
  * Plan a geometry with M = n_subsets ordered subsets (Sec. IV-A: subsets
  * visited in bit-reversal order; Sec. IV-B: views spread uniformly over each
- * subset).  Builds the per-view and per-ray tables in FP64 on the host,
- * stores them as FP32 on the current device, and allocates the workspace
- * (two padded image copies, one image of regularizer gradient, two partial
- * images, one inner-iteration image, one subset residual, reduction
- * buffers, device scalars; 2D also a second pair of padded copies, four
- * x-candidate images and the filtered sinogram of the FBP).
+ * subset) for batch images reconstructed together (the problem statement of
+ * Sec. IV, once per image).  Builds the per-view and per-ray tables in FP64
+ * on the host, stores them as FP32 on the current device, and allocates the
+ * workspace, per image of the batch (two padded image copies, one image of
+ * regularizer gradient, two partial images, one inner-iteration image, one
+ * subset residual, reduction buffers, device scalars; 2D also a second
+ * pair of padded copies and four x-candidate images; 2D and full-turn axial
+ * cone beam the filtered sinogram of the FBP).
  * Errors: LALM_E_INVALID for non-positive sizes, dsd <= dso, a source inside
- * the image's circumscribed cylinder, n_subsets outside [1, n_views], an
- * unsupported detector, more than 256 detector rows or 2^20 channels, or
- * (cone beam) a subset sinogram of 4 GiB or more; LALM_E_NOMEM when
- * allocation fails.
+ * the image's circumscribed cylinder, n_subsets outside [1, n_views], batch
+ * outside [1, 65535 / nz], an unsupported detector, more than 256 detector
+ * rows or 2^20 channels, or (cone beam) a subset sinogram of 4 GiB or more;
+ * LALM_E_NOMEM when allocation fails.
  */
-LALM_API lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_subsets, lalm_plan **out);
+LALM_API lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_subsets, int32_t batch,
+                                        lalm_plan **out);
 
 /*
  * Plan facts (the ordered subsets of Sec. IV-A, visited in bit-reversal
@@ -137,7 +147,8 @@ LALM_API lalm_status lalm_plan_destroy(lalm_plan *plan);
  * Projector: ray-driven Joseph interpolation, one ray per detector-cell
  * centre, sampled at every slice of the in-plane dominant axis, linear (2D)
  * or bilinear (3D) interpolation, zero outside the volume; weight per sample
- * = ray length per slice.
+ * = ray length per slice.  With a batch, x holds B images and out_sub,
+ * y_sub, w_sub B subset arrays.
  */
 LALM_API lalm_status lalm_project_subset(lalm_plan *plan, int32_t m, const float *x, float *out_sub,
                                 const float *y_sub, const float *w_sub, hipStream_t stream);
@@ -151,7 +162,8 @@ LALM_API lalm_status lalm_project_subset(lalm_plan *plan, int32_t m, const float
  * deterministic gather, no atomics): x_out = scale * A_m' r
  * (accumulate = 0) or x_out += scale * A_m' r (accumulate = 1).  r_sub
  * holds the subset's rays ([view][row][bin], as lalm_project_subset's
- * output), x_out is an image; both are caller-owned device arrays.
+ * output), x_out is an image; both are caller-owned device arrays (B subset
+ * arrays and B images with a batch).
  * Errors: LALM_E_INVALID for a null pointer or m outside [0, M).
  */
 LALM_API lalm_status lalm_backproject_subset(lalm_plan *plan, int32_t m, const float *r_sub, float *x_out,
@@ -160,7 +172,8 @@ LALM_API lalm_status lalm_backproject_subset(lalm_plan *plan, int32_t m, const f
 /*
  * SQS denominator (Sec. IV-A): denom = A' (w .* (A 1)) over all subsets,
  * the diagonal majorizer L_diag = diag{A'WA1}.  w_full is the whole
- * subset-major weight sinogram.
+ * subset-major weight sinogram (B of them with a batch; denom then holds
+ * the B denominators).
  */
 LALM_API lalm_status lalm_sqs_denom(lalm_plan *plan, const float *w_full, float *denom, hipStream_t stream);
 
@@ -180,6 +193,7 @@ LALM_API lalm_status lalm_sqs_denom(lalm_plan *plan, const float *w_full, float 
  *                 source), bilinear in (channel, row), weight 1/L^2.
  * The helical cone beam has no such one-pass reconstruction (its rays cover
  * each slice from a different set of angles) and is rejected.
+ * With a batch, y_full holds B sinograms and x_out receives B images.
  * Errors: LALM_E_INVALID for helical plans, scans that are not one full
  * turn, or more than 4096 channels. */
 LALM_API lalm_status lalm_fbp(lalm_plan *plan, const float *y_full, float *x_out, hipStream_t stream);
@@ -192,8 +206,8 @@ LALM_API lalm_status lalm_fbp(lalm_plan *plan, const float *y_full, float *x_out
  * units; pairs leaving the grid are dropped.  nonneg = 1 imposes x >= 0
  * (the box constraint Omega). */
 typedef struct {
-    const float *y, *w, *denom; /* full subset-major sinograms; denom image */
-    double beta, delta;
+    const float *y, *w, *denom; /* full subset-major sinograms; denom image (B of each with a batch) */
+    double beta, delta;         /* the same for every image of a batch */
     int32_t nonneg;
 } lalm_problem;
 
@@ -206,7 +220,12 @@ typedef struct {
  * Barzilai-Borwein history (used only with lalm_options.bb = 1, else may be
  * null / ignored): x_prev, grad_prev are device images holding x and grad at
  * the start of the current iteration (written by the library at every
- * iteration start), alpha the current scale of D_L (set to 1 at step 0). */
+ * iteration start), alpha the current scale of D_L (set to 1 at step 0).
+ * With a batch the images hold B images each, every image has its own
+ * continuation state, and l_b, rho_b, alpha_b are HOST arrays of B entries
+ * (read on resume, written on return; required when B > 1, may be null
+ * when B = 1); l, rho and alpha then mirror image 0 and step counts the
+ * steps the batch has taken (all images step together). */
 typedef struct {
     float *x, *g, *grad;
     int64_t step;
@@ -214,6 +233,8 @@ typedef struct {
     double rho;
     float *x_prev, *grad_prev;
     double alpha;
+    int64_t *l_b;
+    double *rho_b, *alpha_b;
 } lalm_state;
 
 /* continuation: 1 = downward continuation with adaptive restart (Sec. III-B),
@@ -223,8 +244,9 @@ typedef struct {
  * IV-A), 1 .. LALM_MAX_INNER; 1 is one projected, diagonally majorized
  * gradient step (the paper's default), n > 1 costs n - 1 more image passes
  * with a regularizer gradient each.  forced_restart: optional DEVICE array of
- * forced_len bytes indexed by global step; when step < forced_len its value
- * replaces the restart test (replay of a restart sequence).
+ * forced_len bytes indexed by global step ([batch][forced_len] with a
+ * batch); when step < forced_len its value replaces the restart test
+ * (replay of a restart sequence).
  * bb = 1: Barzilai-Borwein acceleration (supplement, eq.
  * scale_factor_alpha_k): the majorizer D_L is replaced by alpha_k D_L with
  * alpha_k = min(1, <s, y> / <s, D_L s>) (FP64), s and y the differences of
@@ -244,8 +266,9 @@ typedef struct {
 } lalm_options;
 
 /* Optional per-step record, DEVICE arrays indexed by global step (entries at
- * step >= capacity are not written): rho used by the step, the restart
- * indicator xi (FP64) and whether the step restarted the continuation. */
+ * step >= capacity are not written; [batch][capacity] with a batch): rho
+ * used by the step, the restart indicator xi (FP64) and whether the step
+ * restarted the continuation. */
 typedef struct {
     double *rho, *xi;
     uint8_t *restart;
@@ -264,24 +287,28 @@ typedef struct {
  *   xi = <g_old - grad+, grad+ - grad_old> in FP64; with continuation,
  *   l <- 0 if xi > 0 else l + 1, and the next step uses rho_l.
  * Synchronizes the stream once at the end to return the continuation state.
- * Errors: LALM_E_INVALID for null pointers or n_inner outside [1, LALM_MAX_INNER]; LALM_E_STATE for
- * a negative step; LALM_E_NONFINITE when xi became non-finite (the state
- * then keeps the last image computed from finite gradients and later steps
- * are skipped).
+ * Errors: LALM_E_INVALID for null pointers (also l_b, rho_b, alpha_b with a
+ * batch) or n_inner outside [1, LALM_MAX_INNER]; LALM_E_STATE for a
+ * negative step or an inconsistent continuation state; LALM_E_NONFINITE
+ * when xi of an image became non-finite (that image keeps the last image
+ * computed from finite gradients and skips its later steps; the other
+ * images of a batch run on).
  */
 LALM_API lalm_status lalm_iterate(lalm_plan *plan, const lalm_problem *prob, lalm_state *state,
                          int64_t n_steps, const lalm_options *opt, const lalm_stats *stats,
                          hipStream_t stream);
 
 /* FP64 monitors (reduced in a fixed order: deterministic). */
-/* out_dev[0..2] = Psi(x), 1/2 ||y - A x||_W^2, R(x)   (Sec. IV, eq. "ct_recon") */
+/* out_dev[0..2] = Psi(x), 1/2 ||y - A x||_W^2, R(x)   (Sec. IV, eq. "ct_recon");
+ * with a batch out_dev[3 b .. 3 b + 2] for image b. */
 LALM_API lalm_status lalm_cost_f64(lalm_plan *plan, const lalm_problem *prob, const float *x,
                           double *out_dev, hipStream_t stream);
 /* out_dev[0] = sum_i a_i b_i over n elements (for the adjoint test). */
 LALM_API lalm_status lalm_dot_f64(lalm_plan *plan, const float *a, const float *b, int64_t n,
                          double *out_dev, hipStream_t stream);
 /* out_dev[0] = RMS of (a - b) over voxels whose centre lies within radius_mm
- * of the rotation axis, all slices (Sec. V: RMS difference in the ROI). */
+ * of the rotation axis, all slices (Sec. V: RMS difference in the ROI);
+ * with a batch out_dev[b] for image b. */
 LALM_API lalm_status lalm_roi_rmsd_f64(lalm_plan *plan, const float *a, const float *b, double radius_mm,
                               double *out_dev, hipStream_t stream);
 

@@ -57,6 +57,7 @@ void prof_collect(lalm_plan *p)
 }
 int subset_nview(const lalm_plan *p, int m) { return (int)(p->slot_offset[m + 1] - p->slot_offset[m]); }
 int64_t subset_ray0(const lalm_plan *p, int m) { return p->slot_offset[m] * p->rays_per_view; }
+int64_t sino_elems(const lalm_plan *p) { return (int64_t)p->nv * p->rays_per_view; }
 
 }  // namespace
 
@@ -67,8 +68,10 @@ extern "C" lalm_status lalm_project_subset(lalm_plan *p, int32_t m, const float 
     if (m < 0 || m >= p->M) return fail(LALM_E_INVALID, "lalm_project_subset: subset out of range");
     HIPCHK("project layout", launch_update(p, UPD_LAYOUT, const_cast<float *>(x), nullptr, nullptr,
                                            nullptr, 0.0f, 0, nullptr, st));
+    // image b's subset arrays follow each other: stride = the subset's rays
+    const int64_t n_m = subset_nview(p, m) * p->rays_per_view;
     HIPCHK("project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), y_sub, w_sub, out_sub, 0, 0,
-                                nullptr, 0, st));
+                                nullptr, 0, st, 0, n_m, n_m));
     return LALM_OK;
 }
 
@@ -81,6 +84,7 @@ extern "C" lalm_status lalm_backproject_subset(lalm_plan *p, int32_t m, const fl
     e.scale = scale;
     e.accumulate = accumulate ? 1 : 0;
     e.out = x_out;
+    e.r_stride = subset_nview(p, m) * p->rays_per_view;
     HIPCHK("backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), r_sub, BP_PLAIN, e, st));
     return LALM_OK;
 }
@@ -92,12 +96,14 @@ extern "C" lalm_status lalm_sqs_denom(lalm_plan *p, const float *w_full, float *
     for (int m = 0; m < p->M; ++m) {
         // the library's own residuals carry each ray's scale (3D)
         HIPCHK("sqs project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), nullptr,
-                                        w_full + subset_ray0(p, m), p->d_r, 0, 0, nullptr, 0, st, 1));
+                                        w_full + subset_ray0(p, m), p->d_r, 0, 0, nullptr, 0, st, 1,
+                                        sino_elems(p), p->max_subset_rays));
         BpEpi e{};
         e.scale = 1.0f;
         e.accumulate = m > 0;
         e.out = denom;
         e.ray_scaled = 1;
+        e.r_stride = p->max_subset_rays;
         HIPCHK("sqs backproject", launch_bp(p, subset_slot0(p, m), subset_nview(p, m), p->d_r, BP_PLAIN, e, st));
     }
     return LALM_OK;
@@ -127,14 +133,23 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     if (!(opt->rho_min > 0.0 && opt->rho_min <= 1.0)) return fail(LALM_E_INVALID, "lalm_iterate: rho_min must lie in (0, 1]");
     if (!opt->continuation && !(opt->rho_fixed > 0.0)) return fail(LALM_E_INVALID, "lalm_iterate: rho_fixed must be positive");
     if (s->step < 0) return fail(LALM_E_STATE, "lalm_iterate: negative state step");
-    if (s->step > 0 && (s->l < 0 || !(s->rho > 0.0) || !std::isfinite(s->rho)))
-        return fail(LALM_E_STATE, "lalm_iterate: inconsistent continuation state");
+    const int B = p->B;
+    if (B > 1 && (!s->l_b || !s->rho_b || !s->alpha_b))
+        return fail(LALM_E_INVALID, "lalm_iterate: a batch needs state.l_b, rho_b and alpha_b");
+    // continuation scalars of image b (the scalar fields for a single image)
+    auto l_of = [&](int b) { return B > 1 ? s->l_b[b] : s->l; };
+    auto rho_of = [&](int b) { return B > 1 ? s->rho_b[b] : s->rho; };
+    auto alpha_of = [&](int b) { return B > 1 ? s->alpha_b[b] : s->alpha; };
+    for (int b = 0; b < B; ++b)
+        if (s->step > 0 && (l_of(b) < 0 || !(rho_of(b) > 0.0) || !std::isfinite(rho_of(b))))
+            return fail(LALM_E_STATE, "lalm_iterate: inconsistent continuation state");
     if (opt->bb) {
         if (!s->x_prev || !s->grad_prev) return fail(LALM_E_INVALID, "lalm_iterate: bb needs state.x_prev and state.grad_prev");
         if (!(opt->bb_alpha_min > 0.0 && opt->bb_alpha_min <= 1.0))
             return fail(LALM_E_INVALID, "lalm_iterate: bb_alpha_min must lie in (0, 1]");
-        if (s->step > 0 && !(s->alpha > 0.0 && s->alpha <= 1.0))
-            return fail(LALM_E_STATE, "lalm_iterate: inconsistent Barzilai-Borwein state");
+        for (int b = 0; b < B; ++b)
+            if (s->step > 0 && !(alpha_of(b) > 0.0 && alpha_of(b) <= 1.0))
+                return fail(LALM_E_STATE, "lalm_iterate: inconsistent Barzilai-Borwein state");
     }
     if (p->n_partials < p->bp_nblocks + 2 * 1024 || p->n_partials < 4096)
         return fail(LALM_E_STATE, "lalm_iterate: reduction workspace too small");
@@ -146,6 +161,8 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     BpEpi e{};
     e.scale = (float)M;
     e.ray_scaled = 1;      // the residuals below come from launch_fp with ray_scaled
+    e.r_stride = p->max_subset_rays;
+    const int64_t S = sino_elems(p), R = p->max_subset_rays;
     e.G = s->grad;
     e.g = s->g;
     e.x = s->x;
@@ -164,17 +181,20 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
     }
 
     if (s->step == 0) {
-        HIPCHK("iterate scalars", launch_set_scalars(p, 0, opt->continuation ? 1.0 : opt->rho_fixed, 0, 1.0, st));
+        for (int b = 0; b < B; ++b)
+            HIPCHK("iterate scalars", launch_set_scalars(p, b, 0, opt->continuation ? 1.0 : opt->rho_fixed, 0, 1.0, st));
         HIPCHK("iterate layout", launch_update(p, UPD_LAYOUT, s->x, nullptr, nullptr, nullptr, 0.0f, 0, nullptr, st));
         const int m0 = p->order[0];
         HIPCHK("iterate init project", launch_fp(p, subset_slot0(p, m0), subset_nview(p, m0),
                                                  prob->y + subset_ray0(p, m0), prob->w + subset_ray0(p, m0),
-                                                 p->d_r, 0, 0, nullptr, 1, st, 1));
+                                                 p->d_r, 0, 0, nullptr, 1, st, 1, S, R));
         HIPCHK("iterate init backproject", launch_bp(p, subset_slot0(p, m0), subset_nview(p, m0), p->d_r,
                                                      BP_INIT, e, st));
     } else {
-        const double rho = opt->continuation ? s->rho : opt->rho_fixed;
-        HIPCHK("iterate scalars", launch_set_scalars(p, s->l, rho, s->step, opt->bb ? s->alpha : 1.0, st));
+        for (int b = 0; b < B; ++b) {
+            const double rho = opt->continuation ? rho_of(b) : opt->rho_fixed;
+            HIPCHK("iterate scalars", launch_set_scalars(p, b, l_of(b), rho, s->step, opt->bb ? alpha_of(b) : 1.0, st));
+        }
         HIPCHK("iterate resume", launch_reg_grad(p, s->x, beta, inv_delta2, st));
     }
     // The continuation decision after a step's back-projection is taken by
@@ -225,11 +245,11 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
             if (f_in)
                 HIPCHK("iterate project", launch_fp_decide(p, subset_slot0(p, m), subset_nview(p, m),
                                                            prob->y + subset_ray0(p, m),
-                                                           prob->w + subset_ray0(p, m), p->d_r, e.cont, st));
+                                                           prob->w + subset_ray0(p, m), p->d_r, e.cont, st, S, R));
             else
                 HIPCHK("iterate project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m),
                                                     prob->y + subset_ray0(p, m), prob->w + subset_ray0(p, m),
-                                                    p->d_r, 0, 0, nullptr, 1, st, 1));
+                                                    p->d_r, 0, 0, nullptr, 1, st, 1, S, R));
         }
         if (!fused) {
             ProfScope ps(p, 2, st);
@@ -246,23 +266,36 @@ extern "C" lalm_status lalm_iterate(lalm_plan *p, const lalm_problem *prob, lalm
         }
         {
             ProfScope ps(p, 0, st);
-            const float *xs = f_in ? p->d_xc + (size_t)((t - 1) % 2) * 2 * nvox : s->x;
-            float *xo = p->d_xc + (size_t)(t % 2) * 2 * nvox;
-            HIPCHK("iterate step", launch_step2d(p, xs, f_in ? xs + nvox : s->x, f_in ? s->x : nullptr,
-                                                 f_out ? xo : nullptr, f_out ? xo + nvox : nullptr, e,
+            // candidates: [step pair][candidate][image of the batch]
+            const size_t cand = (size_t)B * nvox;
+            const float *xs = f_in ? p->d_xc + (size_t)((t - 1) % 2) * 2 * cand : s->x;
+            float *xo = p->d_xc + (size_t)(t % 2) * 2 * cand;
+            HIPCHK("iterate step", launch_step2d(p, xs, f_in ? xs + cand : s->x, f_in ? s->x : nullptr,
+                                                 f_out ? xo : nullptr, f_out ? xo + cand : nullptr, e,
                                                  prob->denom, prob->nonneg, !f_out, st));
         }
         pending = true;
     }
     if (pending) HIPCHK("iterate finalize", launch_finalize(p, e.cont, st));
-    HIPCHK("iterate readback", hipMemcpyAsync(p->h_sc, cur_sc(p), sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK("iterate readback", hipMemcpyAsync(p->h_sc, cur_sc(p), (size_t)B * sizeof(DevScalars),
+                                              hipMemcpyDeviceToHost, st));
     HIPCHK("iterate sync", hipStreamSynchronize(st));
     prof_collect(p);
-    s->step = p->h_sc->step;
-    s->l = p->h_sc->l;
-    s->rho = p->h_sc->rho;
-    s->alpha = p->h_sc->alpha;
-    if (p->h_sc->status)
+    bool nonfinite = false;
+    int64_t step = 0;
+    for (int b = 0; b < B; ++b) {
+        const DevScalars &h = p->h_sc[b];
+        nonfinite = nonfinite || h.status;
+        step = std::max<int64_t>(step, h.step);
+        if (s->l_b) s->l_b[b] = h.l;
+        if (s->rho_b) s->rho_b[b] = h.rho;
+        if (s->alpha_b) s->alpha_b[b] = h.alpha;
+    }
+    s->step = step;
+    s->l = p->h_sc[0].l;
+    s->rho = p->h_sc[0].rho;
+    s->alpha = p->h_sc[0].alpha;
+    if (nonfinite)
         return fail(LALM_E_NONFINITE, "lalm_iterate: non-finite restart indicator; later steps skipped");
     return LALM_OK;
 }
@@ -275,15 +308,22 @@ extern "C" lalm_status lalm_cost_f64(lalm_plan *p, const lalm_problem *prob, con
     if (!(prob->delta > 0.0)) return fail(LALM_E_INVALID, "lalm_cost_f64: need delta > 0");
     HIPCHK("cost layout", launch_update(p, UPD_LAYOUT, const_cast<float *>(x), nullptr, nullptr, nullptr,
                                         0.0f, 0, nullptr, st));
+    const int64_t ntmp = 64 + p->M;        // FP64 scratch per image
     for (int m = 0; m < p->M; ++m) {
         int64_t nblk = 0;
         HIPCHK("cost project", launch_fp(p, subset_slot0(p, m), subset_nview(p, m), prob->y + subset_ray0(p, m),
-                                         prob->w + subset_ray0(p, m), nullptr, 1, 0, &nblk, 0, st));
-        HIPCHK("cost sum", launch_sum_partials(p->d_partials, nblk, p->d_tmp + 8 + m, 1.0, st));
+                                         prob->w + subset_ray0(p, m), nullptr, 1, 0, &nblk, 0, st, 0,
+                                         sino_elems(p), 0));
+        for (int b = 0; b < p->B; ++b)
+            HIPCHK("cost sum", launch_sum_partials(p->d_partials + b * p->n_partials, nblk,
+                                                   p->d_tmp + b * ntmp + 8 + m, 1.0, st));
     }
-    HIPCHK("cost data", launch_sum_partials(p->d_tmp + 8, p->M, p->d_tmp + 0, 1.0, st));
-    HIPCHK("cost reg", launch_reg_value(p, x, prob->beta, prob->delta, p->d_tmp + 1, st));
-    HIPCHK("cost combine", launch_combine_cost(out_dev, p->d_tmp + 0, p->d_tmp + 1, st));
+    for (int b = 0; b < p->B; ++b) {
+        double *t = p->d_tmp + b * ntmp;
+        HIPCHK("cost data", launch_sum_partials(t + 8, p->M, t + 0, 1.0, st));
+        HIPCHK("cost reg", launch_reg_value(p, x + b * p->nvox, prob->beta, prob->delta, t + 1, st));
+        HIPCHK("cost combine", launch_combine_cost(out_dev + 3 * b, t + 0, t + 1, st));
+    }
     return LALM_OK;
 }
 
@@ -300,7 +340,8 @@ extern "C" lalm_status lalm_roi_rmsd_f64(lalm_plan *p, const float *a, const flo
 {
     if (!p || !a || !b || !out_dev || !(radius_mm >= 0.0))
         return fail(LALM_E_INVALID, "lalm_roi_rmsd_f64: bad argument");
-    HIPCHK("rmsd", launch_rmsd(p, a, b, radius_mm, out_dev, st));
+    for (int k = 0; k < p->B; ++k)
+        HIPCHK("rmsd", launch_rmsd(p, a + k * p->nvox, b + k * p->nvox, radius_mm, out_dev + k, st));
     return LALM_OK;
 }
 

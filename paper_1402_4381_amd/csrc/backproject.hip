@@ -42,7 +42,22 @@ struct BPArgs {
     float *part;       // 2D: back-projection of the x-dominant rays
     float *part2;      // 2D: back-projection of the y-dominant rays
     int check_status;  // 2D line kernel: skip when a non-finite indicator was met
+    BatchStr bs;       // batch: image b's residual starts at r + b e.r_stride
 };
+
+// Pointers of BPArgs moved to image bi of the batch.
+__device__ inline void bp_args_at(BPArgs &A, long long bi)
+{
+    A.r += bi * A.e.r_stride;
+    if (A.e.out) A.e.out += bi * A.bs.img;
+    if (A.e.G) A.e.G += bi * A.bs.img;
+    if (A.e.g) A.e.g += bi * A.bs.img;
+    if (A.e.x) A.e.x += bi * A.bs.img;
+    if (A.partials) A.partials += bi * A.bs.part;
+    if (A.sc) A.sc += bi;
+    if (A.part) A.part += bi * A.bs.img;
+    if (A.part2) A.part2 += bi * A.bs.img;
+}
 
 __device__ inline double block_sum_256(double v, double *lds)
 {
@@ -87,11 +102,14 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
 {
     constexpr int KZ = KZ3;
     const GeoK &K = A.k;
+    const unsigned nzb = (unsigned)(K.nz + KZ - 1) / KZ;     // slice blocks per image
+    const int kzb = (int)(blockIdx.z % nzb);
+    bp_args_at(A, blockIdx.z / nzb);
     if (MODE != BP_PLAIN && A.sc->status) return;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + ty * 32;
     const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 8 + ty;
-    const int kb = blockIdx.z * KZ;
+    const int kb = kzb * KZ;
     const bool inside = i < K.nx && j < K.ny;
 
     // detector rows (v_r, cone factor); two padding rows far outside every
@@ -262,7 +280,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
     if (MODE == BP_PLAIN) return;
 
     const double bsum = block_sum_256(part, s_red);
-    const int blin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int blin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * kzb);
     if (tid == 0) A.partials[blin] = bsum;
 }
 
@@ -329,6 +347,7 @@ __device__ inline void splat2(float *slab, int lane_off, float fl, float flo, fl
 __global__ void __launch_bounds__(64 * BP2_VG) bp2d_lines_kernel(BPArgs A, int nxt)
 {
     const GeoK &K = A.k;
+    bp_args_at(A, blockIdx.y);           // image of the batch
     // a stopped run (status set) skips only the writes: every read index
     // depends on the geometry alone, so the status load need not come first
     const int status = A.sc->status;
@@ -474,6 +493,7 @@ template <int MODE>
 __global__ void __launch_bounds__(256) bp2d_epilogue_kernel(BPArgs A)
 {
     const GeoK &K = A.k;
+    bp_args_at(A, blockIdx.z);           // image of the batch
     if (MODE != BP_PLAIN && A.sc->status) return;
     __shared__ double s_red[4];
     const int tid = threadIdx.x + 32 * threadIdx.y;
@@ -522,6 +542,7 @@ struct Step2dArgs {
     float scale, beta, inv_delta2;
     double rho_min;
     int continuation, nonneg;
+    BatchStr bs;            // image b = blockIdx.z
 };
 
 template <bool LAST>
@@ -530,6 +551,27 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
     const GeoK &K = A.k;
     __shared__ float tile[2][32][33];
     __shared__ double s_red[16];
+    {
+        // image bi of the batch
+        const long long bi = blockIdx.z, im = bi * A.bs.img;
+        A.part += im;
+        A.part2 += im;
+        A.G += im;
+        A.g += im;
+        A.xs0 += im;
+        A.xs1 += im;
+        if (A.xw) A.xw += im;
+        if (A.denom) A.denom += im;
+        A.gradR += im;
+        if (A.xo0) A.xo0 += im;
+        if (A.xo1) A.xo1 += im;
+        if (A.XT0) A.XT0 += bi * A.bs.layT;
+        if (A.XN0) A.XN0 += bi * A.bs.layN;
+        if (A.XT1) A.XT1 += bi * A.bs.layT;
+        if (A.XN1) A.XN1 += bi * A.bs.layN;
+        A.sc += bi;
+        A.partials += bi * A.bs.part;
+    }
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + 32 * ty;
     const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
@@ -613,10 +655,16 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
 // bits wherever it is taken.
 template <int MODE, bool WAVE>
 __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, long long nblocks,
-                                                       const DevScalars *in, DevScalars *out, ContArgs C)
+                                                       const DevScalars *in, DevScalars *out, ContArgs C,
+                                                       long long part_stride)
 {
     __shared__ double s_w[4];
     const int tid = threadIdx.x;
+    // one block per image of the batch
+    partials += (long long)blockIdx.x * part_stride;
+    in += blockIdx.x;
+    out += blockIdx.x;
+    C = cont_at(C, (int)blockIdx.x);
     const DevScalars s = *in;
     if (s.status) {
         if (tid == 0) *out = s;
@@ -645,7 +693,11 @@ template <bool IS3D>
 __global__ void __launch_bounds__(256) reg_grad_kernel(GeoK K, const float *x, float *out, float beta,
                                                        float inv_delta2)
 {
-    const int i = blockIdx.x * 32 + threadIdx.x, j = blockIdx.y * 8 + threadIdx.y, k = blockIdx.z;
+    const int i = blockIdx.x * 32 + threadIdx.x, j = blockIdx.y * 8 + threadIdx.y;
+    const int k = (int)(blockIdx.z % (unsigned)K.nz);
+    const long long im = (long long)(blockIdx.z / (unsigned)K.nz) * ((long long)K.nx * K.ny * K.nz);
+    x += im;                               // image of the batch
+    out += im;
     if (i >= K.nx || j >= K.ny) return;
     out[((long long)k * K.ny + j) * K.nx + i] = reg_grad_at<IS3D>(K, x, i, j, k, beta, inv_delta2);
 }
@@ -671,21 +723,23 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.part = p->d_part;
     a.part2 = p->d_part2;
     a.check_status = mode != BP_PLAIN;
+    a.bs = batch_str(p);
     if (!p->is3d) {
         const int nxt = ((p->nx + 63) / 64) * ((p->ny + BP2_TR - 1) / BP2_TR);
         const int nyt = ((p->nx + BP2_TR - 1) / BP2_TR) * ((p->ny + 63) / 64);
-        const hipError_t el = klaunch(p, bp2d_lines_kernel, dim3(nxt + nyt), dim3(64, BP2_VG), st, a, nxt);
+        const hipError_t el = klaunch(p, bp2d_lines_kernel, dim3(nxt + nyt, p->B), dim3(64, BP2_VG), st, a, nxt);
         if (el != hipSuccess || mode == BP_LINES) return el;
         if (mode == BP_STEP) return launch_step2d(p, e.x, e.x, nullptr, nullptr, nullptr, e, nullptr, 0, true, st);
-        dim3 ge((p->nx + 31) / 32, (p->ny + 7) / 8);
+        dim3 ge((p->nx + 31) / 32, (p->ny + 7) / 8, p->B);
         a.nblocks = (int)(ge.x * ge.y);
         if (mode == BP_PLAIN) hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_PLAIN>), ge, dim3(32, 8), 0, st, a);
         else hipLaunchKernelGGL((bp2d_epilogue_kernel<BP_INIT>), ge, dim3(32, 8), 0, st, a);
     } else {
         if (mode == BP_LINES) return hipErrorInvalidValue;
         const int kz = KZ3;
-        dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + kz - 1) / kz);
-        a.nblocks = (int)(grd.x * grd.y * grd.z);
+        const unsigned nzb = (unsigned)(p->nz + kz - 1) / kz;
+        dim3 grd((p->nx + 31) / 32, (p->ny + 7) / 8, nzb * p->B);
+        a.nblocks = (int)(grd.x * grd.y * nzb);
         hipError_t e = bp_dispatch(p, a, mode, grd, st);
         if (e != hipSuccess) return e;
     }
@@ -694,13 +748,13 @@ hipError_t launch_bp(const lalm_plan *p, int64_t slot0, int nview, const float *
     if (mode == BP_INIT) {
         // finite check of the initial gradient: scalars advance to the other record
         if (p->is3d)
-            hipLaunchKernelGGL((finalize_kernel<BP_INIT, false>), dim3(1), dim3(256), 0, st,
+            hipLaunchKernelGGL((finalize_kernel<BP_INIT, false>), dim3(p->B), dim3(256), 0, st,
                                (const double *)p->d_partials, p->bp_nblocks, (const DevScalars *)cur_sc(p),
-                               p->d_sc + (p->sc_cur ^ 1), e.cont);
+                               nxt_sc(p), e.cont, (long long)p->n_partials);
         else
-            hipLaunchKernelGGL((finalize_kernel<BP_INIT, true>), dim3(1), dim3(256), 0, st,
+            hipLaunchKernelGGL((finalize_kernel<BP_INIT, true>), dim3(p->B), dim3(256), 0, st,
                                (const double *)p->d_partials, p->bp_nblocks, (const DevScalars *)cur_sc(p),
-                               p->d_sc + (p->sc_cur ^ 1), e.cont);
+                               nxt_sc(p), e.cont, (long long)p->n_partials);
         p->sc_cur ^= 1;
     }
     return hipGetLastError();
@@ -736,7 +790,8 @@ hipError_t launch_step2d(const lalm_plan *p, const float *xs0, const float *xs1,
     a.rho_min = e.cont.rho_min;
     a.continuation = e.cont.continuation;
     a.nonneg = nonneg;
-    const dim3 grd((p->nx + 31) / 32, (p->ny + 31) / 32);
+    a.bs = batch_str(p);
+    const dim3 grd((p->nx + 31) / 32, (p->ny + 31) / 32, p->B);
     p->bp_nblocks = (long long)grd.x * grd.y;
     return last ? klaunch(p, step2d_kernel<true>, grd, dim3(32, 32), st, a)
                 : klaunch(p, step2d_kernel<false>, grd, dim3(32, 32), st, a);
@@ -746,10 +801,12 @@ hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st
 {
     const double *part = p->d_partials;
     const DevScalars *in = cur_sc(p);
-    DevScalars *out = p->d_sc + (p->sc_cur ^ 1);
+    DevScalars *out = nxt_sc(p);
+    const long long ps = p->n_partials;
+    const dim3 g(p->B);
     const hipError_t e = p->is3d
-        ? klaunch(p, finalize_kernel<BP_STEP, false>, dim3(1), dim3(256), st, part, p->bp_nblocks, in, out, c)
-        : klaunch(p, finalize_kernel<BP_STEP, true>, dim3(1), dim3(256), st, part, p->bp_nblocks, in, out, c);
+        ? klaunch(p, finalize_kernel<BP_STEP, false>, g, dim3(256), st, part, p->bp_nblocks, in, out, c, ps)
+        : klaunch(p, finalize_kernel<BP_STEP, true>, g, dim3(256), st, part, p->bp_nblocks, in, out, c, ps);
     p->sc_cur ^= 1;
     return e;
 }
@@ -757,7 +814,7 @@ hipError_t launch_finalize(const lalm_plan *p, const ContArgs &c, hipStream_t st
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,
                            hipStream_t st)
 {
-    dim3 blk(32, 8), grd((p->nx + 31) / 32, (p->ny + 7) / 8, p->nz);
+    dim3 blk(32, 8), grd((p->nx + 31) / 32, (p->ny + 7) / 8, (unsigned)(p->nz * p->B));
     if (p->is3d)
         hipLaunchKernelGGL((reg_grad_kernel<true>), grd, blk, 0, st, p->k, x, p->d_gradR, beta, inv_delta2);
     else

@@ -26,11 +26,12 @@ constexpr int FBP_NBMAX = 4096;   // channels per view held in LDS
 // block per detector row of a view, the weighted row and the kernel table
 // in LDS, each output summed over k in increasing order.
 __global__ void __launch_bounds__(256) fbp_filter_kernel(const float *y, float *Q, int nb, double dg, double D,
-                                                         double center, int nr, double dt, double dsd)
+                                                         double center, int nr, double dt, double dsd,
+                                                         long long sino_elems)
 {
     __shared__ float q[FBP_NBMAX];
     __shared__ float gk[FBP_NBMAX];
-    const long long base = (long long)blockIdx.x * nb;
+    const long long base = (long long)blockIdx.y * sino_elems + (long long)blockIdx.x * nb;   // image, row
     const double pi = 3.14159265358979323846;
     const double vr = ((double)(blockIdx.x % nr) - (nr - 1) / 2.0) * dt;
     const double Dc = vr == 0.0 ? D : D * (dsd / sqrt(dsd * dsd + vr * vr));
@@ -61,6 +62,8 @@ __global__ void __launch_bounds__(256) fbp_backproject_kernel(GeoK K, const View
                                                               const float *Q, float dbeta, float *x)
 {
     const int i = blockIdx.x * 32 + threadIdx.x, j = blockIdx.y * 8 + threadIdx.y;
+    Q += (long long)blockIdx.z * nview * K.nb;          // image of the batch
+    x += (long long)blockIdx.z * K.nx * K.ny;
     if (i >= K.nx || j >= K.ny) return;
     const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
     float acc = 0.0f;
@@ -92,7 +95,13 @@ __global__ void __launch_bounds__(256) fdk_backproject_kernel(GeoK K, const View
                                                               float *x)
 {
     const int i = blockIdx.x * 32 + threadIdx.x, j = blockIdx.y * 8 + threadIdx.y;
-    const int kb = blockIdx.z * FDK_KZ;
+    const unsigned nzb = (unsigned)(K.nz + FDK_KZ - 1) / FDK_KZ;
+    const int kb = (int)(blockIdx.z % nzb) * FDK_KZ;
+    {
+        const long long bi = blockIdx.z / nzb;           // image of the batch
+        Q += bi * nview * K.nr * (long long)K.nb;
+        x += bi * K.nx * K.ny * (long long)K.nz;
+    }
     if (i >= K.nx || j >= K.ny) return;
     const float X = fmaf((float)i, K.dx, K.x0), Y = fmaf((float)j, K.dy, K.y0);
     float Z[FDK_KZ], acc[FDK_KZ];
@@ -155,15 +164,15 @@ hipError_t launch_fbp(const lalm_plan *p, const float *y, float *x, hipStream_t 
     const double dg = g.ds / g.dsd;
     const double center = (p->nb - 1) / 2.0 + g.channel_offset;
     const int nr = p->is3d ? p->nr : 1;
-    hipLaunchKernelGGL(fbp_filter_kernel, dim3((unsigned)(p->nv * nr)), dim3(256), 0, st, y, p->d_fbpq, p->nb, dg,
-                       g.dso, center, nr, g.dt, g.dsd);
+    hipLaunchKernelGGL(fbp_filter_kernel, dim3((unsigned)(p->nv * nr), p->B), dim3(256), 0, st, y, p->d_fbpq, p->nb,
+                       dg, g.dso, center, nr, g.dt, g.dsd, (long long)p->nv * nr * p->nb);
     const double dbeta = 2.0 * 3.14159265358979323846 / g.n_views_per_turn;
     if (!p->is3d) {
-        dim3 blk(32, 8), grd((p->nx + 31) / 32, (p->ny + 7) / 8);
+        dim3 blk(32, 8), grd((p->nx + 31) / 32, (p->ny + 7) / 8, p->B);
         hipLaunchKernelGGL(fbp_backproject_kernel, grd, blk, 0, st, p->k, (const ViewRec *)p->d_views, p->nv,
                            (const float *)p->d_fbpq, (float)dbeta, x);
     } else {
-        dim3 blk(32, 8), grd((p->nx + 31) / 32, (p->ny + 7) / 8, (p->nz + FDK_KZ - 1) / FDK_KZ);
+        dim3 blk(32, 8), grd((p->nx + 31) / 32, (p->ny + 7) / 8, (unsigned)((p->nz + FDK_KZ - 1) / FDK_KZ * p->B));
         hipLaunchKernelGGL(fdk_backproject_kernel, grd, blk, 0, st, p->k, (const ViewRec *)p->d_views, p->nv,
                            (const float *)p->d_fbpq, (float)dbeta, (float)(g.dsd / g.dt), x);
     }

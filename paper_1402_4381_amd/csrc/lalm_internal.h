@@ -57,6 +57,13 @@ struct DevScalars {
     double alpha;     // Barzilai-Borwein scale of D_L (1 without it)
 };
 
+// Element strides of a batch of images planned together (elements of
+// float or double): an image, one XT / XN layout, the reduction partials of
+// one image.  Kernels add b times these to their pointers for image b.
+struct BatchStr {
+    long long img, layT, layN, part;
+};
+
 // Geometry constants handed to kernels by value.
 struct GeoK {
     int nx, ny, nz, nb, nr;
@@ -77,7 +84,9 @@ struct GeoK {
     long long slabT, slabN;   // elements per slice of the dominant axis
 };
 
-// Continuation bookkeeping (restart rule, rho schedule, statistics).
+// Continuation bookkeeping (restart rule, rho schedule, statistics).  With
+// a batch, element b's forced bits start at forced + b forced_len and its
+// statistics at st_* + b st_cap.
 struct ContArgs {
     int continuation;
     double rho_fixed, rho_min;
@@ -87,6 +96,16 @@ struct ContArgs {
     uint8_t *st_restart;
     long long st_cap;
 };
+
+// Element b of a batch: the forced bits and statistics of that image.
+__host__ __device__ inline ContArgs cont_at(ContArgs c, int b)
+{
+    if (c.forced) c.forced += (long long)b * c.forced_len;
+    if (c.st_rho) c.st_rho += (long long)b * c.st_cap;
+    if (c.st_xi) c.st_xi += (long long)b * c.st_cap;
+    if (c.st_restart) c.st_restart += (long long)b * c.st_cap;
+    return c;
+}
 
 // Fixed-order FP64 sum of v[0..n): thread t < 256 adds v[t], v[t+256], ...
 // in turn, each of the four waves combines its lanes by an xor butterfly,
@@ -310,6 +329,13 @@ __device__ inline DevScalars continuation_update(const DevScalars &in, const Con
 struct lalm_plan {
     lalm_geometry g;
     int M = 0;
+    // images planned together: every image-sized buffer (the caller's and
+    // the plan's workspace) holds B images of nvox voxels one after the
+    // other, every sinogram-sized one B sinograms, and each kernel launch
+    // covers all B
+    int B = 1;
+    int64_t nvox = 0;
+    int64_t layT = 0, layN = 0;         // elements of one image's XT / XN layout
     int nx = 0, ny = 0, nz = 0, nb = 0, nr = 0, nv = 0;
     bool is3d = false;
     int device = 0;
@@ -338,17 +364,17 @@ struct lalm_plan {
     // candidates of two consecutive steps ([2 steps][2 candidates][image])
     float *d_xt1 = nullptr, *d_xn1 = nullptr;
     float *d_xc = nullptr;
-    double *d_partials = nullptr;       // reduction partials
+    double *d_partials = nullptr;       // reduction partials, n_partials per image
     int64_t n_partials = 0;
     // two device scalar records: each continuation decision reads one and
     // writes the other (kernels of a launch that make the decision
     // redundantly per block never see a half-updated record); sc_cur is the
     // host's index of the current one, advanced in launch order
-    lalm::DevScalars *d_sc = nullptr;   // [2]
+    lalm::DevScalars *d_sc = nullptr;   // [2][B]
     mutable int sc_cur = 0;
-    mutable long long bp_nblocks = 0;   // partials written by the last STEP back-projection
-    lalm::DevScalars *h_sc = nullptr;   // pinned host mirror
-    double *d_tmp = nullptr;            // small FP64 scratch (monitors)
+    mutable long long bp_nblocks = 0;   // partials (per image) written by the last STEP back-projection
+    lalm::DevScalars *h_sc = nullptr;   // pinned host mirror [B]
+    double *d_tmp = nullptr;            // small FP64 scratch (monitors), 64 + M per image
     int fp_nseg = 1;
     // optional per-kernel event timing
     // (each timed kernel carries its own start / stop events on its dispatch;
@@ -388,17 +414,24 @@ inline hipError_t klaunch(const lalm_plan *p, K kernel, dim3 grid, dim3 block, h
 // ray_scaled (3D, mode 0): each ray's entry is further multiplied by the
 // ray's scale (in-plane length factor times the row's cone factor), which a
 // back-projection with BpEpi::ray_scaled then leaves out.
+// With a batch, image b's y and w start at y + b yw_stride, its output at
+// out + b out_stride and its partials at partials + b n_partials + part_off.
 hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *y,
                      const float *w, float *out, int mode, int64_t part_off,
-                     int64_t *n_blocks_out, int check_status, hipStream_t st, int ray_scaled = 0);
+                     int64_t *n_blocks_out, int check_status, hipStream_t st, int ray_scaled,
+                     int64_t yw_stride, int64_t out_stride);
 
-inline lalm::DevScalars *cur_sc(const lalm_plan *p) { return p->d_sc + p->sc_cur; }
+// The current scalar records (one per image) and the other set.
+inline lalm::DevScalars *cur_sc(const lalm_plan *p) { return p->d_sc + (size_t)p->sc_cur * p->B; }
+inline lalm::DevScalars *nxt_sc(const lalm_plan *p) { return p->d_sc + (size_t)(p->sc_cur ^ 1) * p->B; }
+inline BatchStr batch_str(const lalm_plan *p) { return BatchStr{p->nvox, p->layT, p->layN, p->n_partials}; }
 // The same forward projection, first taking the continuation decision of
 // the previous step (every wave reduces the fused step kernel's partials in
 // the same fixed order; one thread records it in the other scalar record)
 // and reading the projector layouts of the candidate it selects.
 hipError_t launch_fp_decide(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
-                            float *out, const ContArgs &cont, hipStream_t st);
+                            float *out, const ContArgs &cont, hipStream_t st, int64_t yw_stride,
+                            int64_t out_stride);
 
 // BP_LINES (2D): the partial back-projections of a STEP only; the fused
 // step kernel (launch_step2d) follows.
@@ -412,6 +445,7 @@ struct BpEpi {
     float beta, inv_delta2;   // regularizer: beta, 1/delta^2
     ContArgs cont;
     int ray_scaled;        // 3D: r already carries each ray's scale (launch_fp ray_scaled)
+    long long r_stride;    // batch: image b's residual starts at r + b r_stride
 };
 // BP_INIT includes its finite check (the scalars advance); BP_STEP leaves
 // the continuation decision of the step to the next x-update or to
@@ -450,7 +484,7 @@ hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zou
                         bool last, hipStream_t st);
 hipError_t launch_reg_grad(const lalm_plan *p, const float *x, float beta, float inv_delta2,
                            hipStream_t st);
-hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step, double alpha,
+hipError_t launch_set_scalars(const lalm_plan *p, int b, long long l, double rho, long long step, double alpha,
                               hipStream_t st);
 // Barzilai-Borwein step at an iteration start: with compute, alpha in the
 // current scalar record from s = x - x_prev, y = grad - grad_prev (FP64,

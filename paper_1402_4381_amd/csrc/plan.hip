@@ -119,7 +119,7 @@ static void free_plan(lalm_plan *p)
     delete p;
 }
 
-extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_subsets,
+extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_subsets, int32_t batch,
                                           lalm_plan **out)
 {
     if (!geom || !out) return invalid("lalm_plan_geometry: null argument");
@@ -141,6 +141,8 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     if (g.detector != 0) return invalid("geometry: only the arc detector (0) is implemented");
     if (g.kind == LALM_CONE_HELICAL && !(g.pitch >= 0)) return invalid("geometry: negative pitch");
     if (n_subsets < 1 || n_subsets > g.n_views) return invalid("n_subsets must lie in [1, n_views]");
+    // kernels index the images of a batch along a grid dimension with the slices
+    if (batch < 1 || (int64_t)batch * g.nz > 65535) return invalid("batch must lie in [1, 65535 / nz]");
     if (g.n_rows > 256) return invalid("geometry: at most 256 detector rows");
     // the cone back-projector forms row offsets row * n_bins with 24-bit
     // multiplies and gathers a subset's residual by 32-bit byte offsets
@@ -154,6 +156,7 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     lalm_plan *p = new lalm_plan();
     p->g = g;
     p->M = n_subsets;
+    p->B = batch;
     p->nx = g.nx; p->ny = g.ny; p->nz = g.nz; p->nb = g.n_bins; p->nr = g.n_rows; p->nv = g.n_views;
     p->is3d = g.kind != LALM_FAN2D;
     (void)hipGetDevice(&p->device);
@@ -312,6 +315,10 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     while (p->fp_nseg < 8 && waves * p->fp_nseg < 8192) p->fp_nseg *= 2;
 
     const size_t nvox = (size_t)g.nx * g.ny * g.nz;
+    p->nvox = (int64_t)nvox;
+    p->layT = (int64_t)g.nx * K.slabT;
+    p->layN = (int64_t)g.ny * K.slabN;
+    const size_t Bn = (size_t)batch;          // every per-image buffer holds the batch's images
     const int64_t bp_blocks = (int64_t)((g.nx + 31) / 32) * ((g.ny + 7) / 8) * ((g.nz + 7) / 8);
     p->n_partials = std::max<int64_t>({65536, bp_blocks + 16, (p->max_subset_rays + 63) / 64 + 16,
                                        (int64_t)M + 16});
@@ -322,25 +329,26 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(dev_alloc(&p->d_views, views.size()));
     chk(dev_alloc(&p->d_rowv, (size_t)nr));
     chk(dev_alloc(&p->d_rowf, (size_t)nr));
-    chk(dev_alloc(&p->d_xt, (size_t)g.nx * K.slabT));
-    chk(dev_alloc(&p->d_xn, (size_t)g.ny * K.slabN));
-    chk(dev_alloc(&p->d_gradR, nvox));
-    chk(dev_alloc(&p->d_r, (size_t)p->max_subset_rays));
-    chk(dev_alloc(&p->d_part, nvox));
-    chk(dev_alloc(&p->d_part2, nvox));
-    chk(dev_alloc(&p->d_v, nvox));
+    chk(dev_alloc(&p->d_xt, Bn * p->layT));
+    chk(dev_alloc(&p->d_xn, Bn * p->layN));
+    chk(dev_alloc(&p->d_gradR, Bn * nvox));
+    chk(dev_alloc(&p->d_r, Bn * (size_t)p->max_subset_rays));
+    chk(dev_alloc(&p->d_part, Bn * nvox));
+    chk(dev_alloc(&p->d_part2, Bn * nvox));
+    chk(dev_alloc(&p->d_v, Bn * nvox));
     // filtered sinogram of the initial image (fan-beam FBP, axial FDK)
     if (!is3d || (g.kind == LALM_CONE_AXIAL && g.n_views == g.n_views_per_turn))
-        chk(dev_alloc(&p->d_fbpq, (size_t)p->nv * nr * p->nb));
+        chk(dev_alloc(&p->d_fbpq, Bn * (size_t)p->nv * nr * p->nb));
     if (!is3d) {
-        chk(dev_alloc(&p->d_xt1, (size_t)g.nx * K.slabT));
-        chk(dev_alloc(&p->d_xn1, (size_t)g.ny * K.slabN));
-        chk(dev_alloc(&p->d_xc, 4 * nvox));
+        chk(dev_alloc(&p->d_xt1, Bn * p->layT));
+        chk(dev_alloc(&p->d_xn1, Bn * p->layN));
+        chk(dev_alloc(&p->d_xc, 4 * Bn * nvox));      // [step pair][candidate][image]
     }
-    chk(dev_alloc(&p->d_partials, (size_t)p->n_partials));
-    chk(dev_alloc(&p->d_sc, 2));
-    chk(dev_alloc(&p->d_tmp, (size_t)(64 + M)));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_sc, sizeof(lalm::DevScalars), hipHostMallocDefault);
+    chk(dev_alloc(&p->d_partials, Bn * (size_t)p->n_partials));
+    chk(dev_alloc(&p->d_sc, 2 * Bn));
+    chk(dev_alloc(&p->d_tmp, Bn * (size_t)(64 + M)));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&p->h_sc, Bn * sizeof(lalm::DevScalars), hipHostMallocDefault);
     if (e != hipSuccess) {
         lalm::set_error(std::string("plan allocation failed: ") + hipGetErrorString(e));
         free_plan(p);
@@ -351,14 +359,15 @@ extern "C" lalm_status lalm_plan_geometry(const lalm_geometry *geom, int32_t n_s
     chk(hipMemcpy(p->d_views, views.data(), views.size() * sizeof(lalm::ViewRec), hipMemcpyHostToDevice));
     chk(hipMemcpy(p->d_rowv, rowv.data(), nr * sizeof(float), hipMemcpyHostToDevice));
     chk(hipMemcpy(p->d_rowf, rowf.data(), nr * sizeof(float), hipMemcpyHostToDevice));
-    chk(hipMemset(p->d_xt, 0, (size_t)g.nx * K.slabT * sizeof(float)));
-    chk(hipMemset(p->d_xn, 0, (size_t)g.ny * K.slabN * sizeof(float)));
+    // the layouts' zero borders are written once, here, and never again
+    chk(hipMemset(p->d_xt, 0, Bn * p->layT * sizeof(float)));
+    chk(hipMemset(p->d_xn, 0, Bn * p->layN * sizeof(float)));
     if (!is3d) {
-        chk(hipMemset(p->d_xt1, 0, (size_t)g.nx * K.slabT * sizeof(float)));
-        chk(hipMemset(p->d_xn1, 0, (size_t)g.ny * K.slabN * sizeof(float)));
+        chk(hipMemset(p->d_xt1, 0, Bn * p->layT * sizeof(float)));
+        chk(hipMemset(p->d_xn1, 0, Bn * p->layN * sizeof(float)));
     }
-    chk(hipMemset(p->d_gradR, 0, nvox * sizeof(float)));
-    chk(hipMemset(p->d_sc, 0, 2 * sizeof(lalm::DevScalars)));
+    chk(hipMemset(p->d_gradR, 0, Bn * nvox * sizeof(float)));
+    chk(hipMemset(p->d_sc, 0, 2 * Bn * sizeof(lalm::DevScalars)));
     chk(hipDeviceSynchronize());
     if (e != hipSuccess) {
         lalm::set_error(std::string("plan upload failed: ") + hipGetErrorString(e));

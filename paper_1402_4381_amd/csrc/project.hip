@@ -27,7 +27,7 @@ struct FPArgs {
     const float *y, *w;
     float *out;
     double *partials;       // mode 1
-    const int *status;      // skip when set (LALM steps only)
+    const DevScalars *st_sc;   // skip when its status is set (LALM steps only)
     // DEC: the pending continuation decision, then the selected layouts
     const float *XT1, *XN1;
     const DevScalars *sc_in;
@@ -36,6 +36,10 @@ struct FPArgs {
     long long dec_n;
     ContArgs cont;
     int ray_scaled;         // 3D mode 0: out also carries the ray's scale
+    // batch: image b = blockIdx.y; its y and w start b s_yw further, its
+    // output b s_out further
+    BatchStr bs;
+    long long s_yw, s_out;
 };
 
 constexpr int FP3_U = 8;   // 3D: samples whose taps are loaded together
@@ -70,6 +74,23 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 {
     const GeoK &K = A.k;
     const int lane = threadIdx.x, seg = threadIdx.y;
+    {
+        // image bi of the batch
+        const long long bi = blockIdx.y;
+        A.XT += bi * A.bs.layT;
+        A.XN += bi * A.bs.layN;
+        if (A.XT1) A.XT1 += bi * A.bs.layT;
+        if (A.XN1) A.XN1 += bi * A.bs.layN;
+        if (A.y) A.y += bi * A.s_yw;
+        if (A.w) A.w += bi * A.s_yw;
+        if (A.out) A.out += bi * A.s_out;
+        if (A.partials) A.partials += bi * A.bs.part;
+        if (A.st_sc) A.st_sc += bi;
+        if (A.sc_in) A.sc_in += bi;
+        if (A.sc_out) A.sc_out += bi;
+        if (A.dec_part) A.dec_part += bi * A.bs.part;
+        A.cont = cont_at(A.cont, (int)bi);
+    }
     const long long q = (long long)blockIdx.x * 64 + lane;
     const bool valid = q < A.nrays;
     float acc = 0.0f;
@@ -106,7 +127,7 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
             XT = A.XT1;
             XN = A.XN1;
         }
-    } else if (A.status && *A.status) {
+    } else if (A.st_sc && A.st_sc->status) {
         return;
     }
     if (valid) {
@@ -227,7 +248,7 @@ __global__ void __launch_bounds__(64 * NSEG) fp_kernel(FPArgs A)
 template <bool IS3D, int NSEG>
 hipError_t fp_dispatch_mode(const lalm_plan *p, const FPArgs &a, int mode, long long nblk, hipStream_t st)
 {
-    dim3 blk(64, NSEG), grd((unsigned)nblk);
+    dim3 blk(64, NSEG), grd((unsigned)nblk, (unsigned)p->B);
     // mode 2: mode 0 after the pending continuation decision (2D)
     if (mode == 0) return klaunch(p, fp_kernel<IS3D, NSEG, 0, false>, grd, blk, st, a);
     if (mode == 1) return klaunch(p, fp_kernel<IS3D, NSEG, 1, false>, grd, blk, st, a);
@@ -267,6 +288,7 @@ struct UpdArgs {
     ContArgs cont;
     // first of several inner iterations: v and the next momentum point go here
     float *vout, *zout;
+    BatchStr bs;            // image b = blockIdx.z / nz
 };
 
 template <bool IS3D, int MODE>
@@ -275,7 +297,24 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
     const GeoK &K = A.k;
     __shared__ float tile[32][33];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int k = blockIdx.z;
+    const int k = (int)(blockIdx.z % (unsigned)K.nz);
+    {
+        // image bi of the batch
+        const long long bi = blockIdx.z / (unsigned)K.nz;
+        if (A.x) A.x += bi * A.bs.img;
+        if (A.G) A.G += bi * A.bs.img;
+        if (A.g) A.g += bi * A.bs.img;
+        if (A.gradR) A.gradR += bi * A.bs.img;
+        if (A.denom) A.denom += bi * A.bs.img;
+        A.XT += bi * A.bs.layT;
+        A.XN += bi * A.bs.layN;
+        A.sc += bi;
+        A.sc_out += bi;
+        if (A.partials) A.partials += bi * A.bs.part;
+        A.cont = cont_at(A.cont, (int)bi);
+        if (A.vout) A.vout += bi * A.bs.img;
+        if (A.zout) A.zout += bi * A.bs.img;
+    }
     const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
     const bool inside = i < K.nx && j < K.ny;
     const long long idx = ((long long)k * K.ny + j) * K.nx + i;
@@ -299,7 +338,7 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         if (A.do_finalize) {
             // every wave takes the same decision from the same fixed-order
             // sum; the first thread records it in the other scalar record
-            const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tx == 0 && ty == 0;
+            const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && k == 0 && tx == 0 && ty == 0;
             if (!s.status) {
                 const double xi = fixed_sum_wave(A.partials, A.nblocks, (tx + 32 * ty) & 63);
                 s = continuation_update(s, A.cont, xi, false, lead);
@@ -352,6 +391,7 @@ struct InnerArgs {
     const DevScalars *sc;
     float beta, inv_delta2, mom;
     int nonneg;
+    BatchStr bs;            // image b = blockIdx.z / nz
 };
 
 template <bool IS3D, bool LAST>
@@ -359,11 +399,25 @@ __global__ void __launch_bounds__(1024) inner_kernel(InnerArgs A)
 {
     const GeoK &K = A.k;
     __shared__ float tile[32][33];
+    const int k = (int)(blockIdx.z % (unsigned)K.nz);
+    {
+        // image bi of the batch
+        const long long bi = blockIdx.z / (unsigned)K.nz;
+        A.z += bi * A.bs.img;
+        A.G += bi * A.bs.img;
+        A.g += bi * A.bs.img;
+        A.denom += bi * A.bs.img;
+        A.v += bi * A.bs.img;
+        if (A.zout) A.zout += bi * A.bs.img;
+        A.x += bi * A.bs.img;
+        A.XT += bi * A.bs.layT;
+        A.XN += bi * A.bs.layN;
+        A.sc += bi;
+    }
     const DevScalars s = *A.sc;
     if (s.status) return;
     const float rho = (float)s.rho;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int k = blockIdx.z;
     const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
     const bool inside = i < K.nx && j < K.ny;
     float v = 0.0f;
@@ -403,7 +457,7 @@ __global__ void __launch_bounds__(1024) inner_kernel(InnerArgs A)
 template <bool IS3D>
 hipError_t upd_dispatch(const lalm_plan *p, const UpdArgs &a, int mode, hipStream_t st)
 {
-    dim3 blk(32, 32), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, a.k.nz);
+    dim3 blk(32, 32), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, (unsigned)(a.k.nz * p->B));
     if (mode == UPD_LAYOUT) return klaunch(p, update_kernel<IS3D, UPD_LAYOUT>, grd, blk, st, a);
     if (mode == UPD_ONES) return klaunch(p, update_kernel<IS3D, UPD_ONES>, grd, blk, st, a);
     return klaunch(p, update_kernel<IS3D, UPD_STEP>, grd, blk, st, a);
@@ -429,10 +483,21 @@ __global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long
 constexpr int BB_BLOCKS = 1024;
 
 __global__ void __launch_bounds__(256) bb_dot_kernel(const float *x, const float *grad, float *xp, float *gp,
-                                                     const float *denom, long long n, int compute, double *part)
+                                                     const float *denom, long long n, int compute, double *part,
+                                                     long long part_stride)
 {
     __shared__ double s_w[2][4];
     const int tid = threadIdx.x;
+    {
+        // image bi of the batch (n voxels each)
+        const long long bi = blockIdx.y;
+        x += bi * n;
+        grad += bi * n;
+        xp += bi * n;
+        gp += bi * n;
+        denom += bi * n;
+        part += bi * part_stride;
+    }
     double sy = 0.0, sls = 0.0;
     for (long long i = (long long)blockIdx.x * 256 + tid; i < n; i += (long long)gridDim.x * 256) {
         const float xv = x[i], gv = grad[i];
@@ -463,9 +528,12 @@ __global__ void __launch_bounds__(256) bb_dot_kernel(const float *x, const float
 
 // alpha = min(1, <s,y> / <s,D_L s>), at least alpha_min; 1 without curvature
 // information (non-positive sums).  Written into the current scalar record.
-__global__ void __launch_bounds__(256) bb_finalize_kernel(const double *part, DevScalars *sc, double alpha_min)
+__global__ void __launch_bounds__(256) bb_finalize_kernel(const double *part, DevScalars *sc, double alpha_min,
+                                                          long long part_stride)
 {
     __shared__ double s_w[4];
+    part += (long long)blockIdx.x * part_stride;     // one block per image
+    sc += blockIdx.x;
     if (sc->status) return;
     const int tid = threadIdx.x;
     const double sy = fixed_sum_256(part, BB_BLOCKS, tid, s_w);
@@ -477,7 +545,7 @@ __global__ void __launch_bounds__(256) bb_finalize_kernel(const double *part, De
 
 hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
                      float *out, int mode, int64_t part_off, int64_t *n_blocks_out,
-                     int check_status, hipStream_t st, int ray_scaled)
+                     int check_status, hipStream_t st, int ray_scaled, int64_t yw_stride, int64_t out_stride)
 {
     FPArgs a;
     a.k = p->k;
@@ -493,7 +561,7 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.w = w;
     a.out = out;
     a.partials = p->d_partials + part_off;
-    a.status = check_status ? &cur_sc(p)->status : nullptr;
+    a.st_sc = check_status ? cur_sc(p) : nullptr;
     a.XT1 = a.XN1 = nullptr;
     a.sc_in = nullptr;
     a.sc_out = nullptr;
@@ -501,6 +569,9 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
     a.dec_n = 0;
     a.cont = ContArgs{};
     a.ray_scaled = ray_scaled;
+    a.bs = batch_str(p);
+    a.s_yw = yw_stride;
+    a.s_out = out_stride;
     long long nblk = (a.nrays + 63) / 64;
     if (n_blocks_out) *n_blocks_out = nblk;
     if (nblk == 0) return hipSuccess;
@@ -509,7 +580,8 @@ hipError_t launch_fp(const lalm_plan *p, int64_t slot0, int nview, const float *
 }
 
 hipError_t launch_fp_decide(const lalm_plan *p, int64_t slot0, int nview, const float *y, const float *w,
-                            float *out, const ContArgs &cont, hipStream_t st)
+                            float *out, const ContArgs &cont, hipStream_t st, int64_t yw_stride,
+                            int64_t out_stride)
 {
     if (p->is3d || !p->d_xt1 || !p->d_xn1) return hipErrorInvalidValue;
     FPArgs a;
@@ -528,13 +600,16 @@ hipError_t launch_fp_decide(const lalm_plan *p, int64_t slot0, int nview, const 
     a.w = w;
     a.out = out;
     a.partials = nullptr;
-    a.status = nullptr;
+    a.st_sc = nullptr;
     a.sc_in = cur_sc(p);
-    a.sc_out = p->d_sc + (p->sc_cur ^ 1);
+    a.sc_out = nxt_sc(p);
     a.dec_part = p->d_partials;
     a.dec_n = p->bp_nblocks;
     a.cont = cont;
     a.ray_scaled = 0;       // 2D residuals carry no ray scale
+    a.bs = batch_str(p);
+    a.s_yw = yw_stride;
+    a.s_out = out_stride;
     const long long nblk = (a.nrays + 63) / 64;
     if (nblk == 0) return hipErrorInvalidValue;     // every subset holds a view
     const hipError_t e = fp_dispatch<false>(p, a, p->fp_nseg, 2, nblk, st);
@@ -561,11 +636,12 @@ hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G,
     a.do_finalize = (mode == UPD_STEP && cont) ? 1 : 0;
     a.partials = p->d_partials;
     a.nblocks = p->bp_nblocks;
-    a.sc_out = p->d_sc + (p->sc_cur ^ 1);
+    a.sc_out = nxt_sc(p);
     if (a.do_finalize) a.cont = *cont;
     else a.cont = ContArgs{};
     a.vout = mode == UPD_STEP ? vout : nullptr;
     a.zout = mode == UPD_STEP ? zout : nullptr;
+    a.bs = batch_str(p);
     hipError_t e = p->is3d ? upd_dispatch<true>(p, a, mode, st) : upd_dispatch<false>(p, a, mode, st);
     if (a.do_finalize) p->sc_cur ^= 1;
     return e;
@@ -591,17 +667,18 @@ hipError_t launch_inner(const lalm_plan *p, const float *z, float *v, float *zou
     a.inv_delta2 = inv_delta2;
     a.mom = mom;
     a.nonneg = nonneg;
-    dim3 blk(32, 32), grd((p->nx + 31) / 32, (p->ny + 31) / 32, p->nz);
+    a.bs = batch_str(p);
+    dim3 blk(32, 32), grd((p->nx + 31) / 32, (p->ny + 31) / 32, (unsigned)(p->nz * p->B));
     if (p->is3d) return last ? klaunch(p, inner_kernel<true, true>, grd, blk, st, a)
                              : klaunch(p, inner_kernel<true, false>, grd, blk, st, a);
     return last ? klaunch(p, inner_kernel<false, true>, grd, blk, st, a)
                 : klaunch(p, inner_kernel<false, false>, grd, blk, st, a);
 }
 
-hipError_t launch_set_scalars(const lalm_plan *p, long long l, double rho, long long step, double alpha,
+hipError_t launch_set_scalars(const lalm_plan *p, int b, long long l, double rho, long long step, double alpha,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, cur_sc(p), l, rho, step, alpha);
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, st, cur_sc(p) + b, l, rho, step, alpha);
     return hipGetLastError();
 }
 
@@ -611,10 +688,10 @@ hipError_t launch_bb(const lalm_plan *p, const float *x, const float *grad, floa
     // the last 2 x BB_BLOCKS partial slots, above any back-projection's block partials
     double *part = p->d_partials + p->n_partials - 2 * BB_BLOCKS;
     const long long n = (long long)p->nx * p->ny * p->nz;
-    hipLaunchKernelGGL(bb_dot_kernel, dim3(BB_BLOCKS), dim3(256), 0, st, x, grad, x_prev, grad_prev, denom, n,
-                       compute ? 1 : 0, part);
-    if (compute) hipLaunchKernelGGL(bb_finalize_kernel, dim3(1), dim3(256), 0, st, (const double *)part, cur_sc(p),
-                                    alpha_min);
+    hipLaunchKernelGGL(bb_dot_kernel, dim3(BB_BLOCKS, p->B), dim3(256), 0, st, x, grad, x_prev, grad_prev, denom, n,
+                       compute ? 1 : 0, part, (long long)p->n_partials);
+    if (compute) hipLaunchKernelGGL(bb_finalize_kernel, dim3(p->B), dim3(256), 0, st, (const double *)part, cur_sc(p),
+                                    alpha_min, (long long)p->n_partials);
     return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ class Problem(ctypes.Structure):
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("g", ctypes.c_void_p), ("grad", ctypes.c_void_p),
                 ("step", ctypes.c_int64), ("l", ctypes.c_int64), ("rho", ctypes.c_double),
-                ("x_prev", ctypes.c_void_p), ("grad_prev", ctypes.c_void_p), ("alpha", ctypes.c_double)]
+                ("x_prev", ctypes.c_void_p), ("grad_prev", ctypes.c_void_p), ("alpha", ctypes.c_double),
+                ("l_b", ctypes.c_void_p), ("rho_b", ctypes.c_void_p), ("alpha_b", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -77,7 +78,7 @@ def _load():
     sig = {
         "lalm_last_error": ([], ctypes.c_char_p),
         "lalm_version": ([], ctypes.c_char_p),
-        "lalm_plan_geometry": ([ctypes.POINTER(Geometry), I32, ctypes.POINTER(P)], I32),
+        "lalm_plan_geometry": ([ctypes.POINTER(Geometry), I32, I32, ctypes.POINTER(P)], I32),
         "lalm_plan_info": ([P, P, P, P, P, P, P], I32),
         "lalm_plan_destroy": ([P], I32),
         "lalm_project_subset": ([P, I32, P, P, P, P, P], I32),
@@ -152,12 +153,15 @@ def lalm_last_error():
 
 
 class Plan:
-    """Owner of a ``lalm_plan`` handle and its host-side facts."""
+    """Owner of a ``lalm_plan`` handle and its host-side facts.  ``batch``
+    images are planned together; image_elems and sino_elems are those of
+    one image."""
 
-    def __init__(self, handle, geom, n_subsets):
+    def __init__(self, handle, geom, n_subsets, batch=1):
         self.handle = handle
         self.geom = dict(geom)
         self.M = n_subsets
+        self.B = int(batch)
         n_views = geom["n_views"]
         img = ctypes.c_int64()
         sino = ctypes.c_int64()
@@ -220,11 +224,12 @@ def _geometry(geom):
     return g
 
 
-def lalm_plan_geometry(geom, n_subsets):
-    """Plan a geometry (a dict with the ``lalm_geometry`` fields)."""
+def lalm_plan_geometry(geom, n_subsets, batch=1):
+    """Plan a geometry (a dict with the ``lalm_geometry`` fields) for
+    ``batch`` images reconstructed together."""
     h = ctypes.c_void_p()
-    _check(_lib.lalm_plan_geometry(ctypes.byref(_geometry(geom)), int(n_subsets), ctypes.byref(h)))
-    return Plan(h, geom, int(n_subsets))
+    _check(_lib.lalm_plan_geometry(ctypes.byref(_geometry(geom)), int(n_subsets), int(batch), ctypes.byref(h)))
+    return Plan(h, geom, int(n_subsets), int(batch))
 
 
 def lalm_plan_info(plan):
@@ -240,54 +245,64 @@ def lalm_plan_destroy(plan):
 
 
 def lalm_project_subset(plan, m, x, out, y=None, w=None, stream=None):
-    n = plan.subset_rays(m)
-    _check(_lib.lalm_project_subset(plan.handle, int(m), _dev(x, "x", numel=plan.image_elems),
+    n = plan.subset_rays(m) * plan.B
+    _check(_lib.lalm_project_subset(plan.handle, int(m), _dev(x, "x", numel=plan.image_elems * plan.B),
                                     _dev(out, "out", numel=n), _dev(y, "y", numel=n, allow_none=True),
                                     _dev(w, "w", numel=n, allow_none=True), _stream(stream)))
 
 
 def lalm_backproject_subset(plan, m, r, x_out, scale=1.0, accumulate=False, stream=None):
-    _check(_lib.lalm_backproject_subset(plan.handle, int(m), _dev(r, "r", numel=plan.subset_rays(m)),
-                                        _dev(x_out, "x_out", numel=plan.image_elems), float(scale),
+    _check(_lib.lalm_backproject_subset(plan.handle, int(m), _dev(r, "r", numel=plan.subset_rays(m) * plan.B),
+                                        _dev(x_out, "x_out", numel=plan.image_elems * plan.B), float(scale),
                                         1 if accumulate else 0, _stream(stream)))
 
 
 def lalm_sqs_denom(plan, w_full, denom, stream=None):
-    _check(_lib.lalm_sqs_denom(plan.handle, _dev(w_full, "w_full", numel=plan.sino_elems),
-                               _dev(denom, "denom", numel=plan.image_elems), _stream(stream)))
+    _check(_lib.lalm_sqs_denom(plan.handle, _dev(w_full, "w_full", numel=plan.sino_elems * plan.B),
+                               _dev(denom, "denom", numel=plan.image_elems * plan.B), _stream(stream)))
 
 
 def lalm_fbp(plan, y_full, x_out, stream=None):
-    _check(_lib.lalm_fbp(plan.handle, _dev(y_full, "y_full", numel=plan.sino_elems),
-                         _dev(x_out, "x_out", numel=plan.image_elems), _stream(stream)))
+    _check(_lib.lalm_fbp(plan.handle, _dev(y_full, "y_full", numel=plan.sino_elems * plan.B),
+                         _dev(x_out, "x_out", numel=plan.image_elems * plan.B), _stream(stream)))
 
 
 def _problem(plan, y, w, denom, beta, delta, nonneg):
-    return Problem(_dev(y, "y", numel=plan.sino_elems), _dev(w, "w", numel=plan.sino_elems),
-                   _dev(denom, "denom", numel=plan.image_elems) if denom is not None else None,
+    B = plan.B
+    return Problem(_dev(y, "y", numel=plan.sino_elems * B), _dev(w, "w", numel=plan.sino_elems * B),
+                   _dev(denom, "denom", numel=plan.image_elems * B) if denom is not None else None,
                    float(beta), float(delta), 1 if nonneg else 0)
 
 
 class LalmState:
     """Caller-owned iteration state: GPU images x, g, grad, the scalars and,
     for the Barzilai-Borwein option, the images at the start of the current
-    iteration (x_prev, grad_prev) and the scale alpha."""
+    iteration (x_prev, grad_prev) and the scale alpha.  For a batch of B
+    images the tensors hold B images and ``l_b``, ``rho_b``, ``alpha_b``
+    (numpy arrays of B entries) the continuation state of each image; the
+    scalar fields then mirror image 0."""
 
-    def __init__(self, x, g, grad, step=0, l=0, rho=1.0, x_prev=None, grad_prev=None, alpha=1.0):
+    def __init__(self, x, g, grad, step=0, l=0, rho=1.0, x_prev=None, grad_prev=None, alpha=1.0, batch=1):
         self.x, self.g, self.grad = x, g, grad
         self.step, self.l, self.rho = int(step), int(l), float(rho)
         self.x_prev, self.grad_prev, self.alpha = x_prev, grad_prev, float(alpha)
+        self.batch = int(batch)
+        self.l_b = np.full(self.batch, self.l, dtype=np.int64)
+        self.rho_b = np.full(self.batch, self.rho, dtype=np.float64)
+        self.alpha_b = np.full(self.batch, self.alpha, dtype=np.float64)
 
     @classmethod
-    def zeros_like(cls, x, bb=False):
+    def zeros_like(cls, x, bb=False, batch=1):
         import torch
         z = torch.zeros_like
-        return cls(x, z(x), z(x), x_prev=z(x) if bb else None, grad_prev=z(x) if bb else None)
+        return cls(x, z(x), z(x), x_prev=z(x) if bb else None, grad_prev=z(x) if bb else None, batch=batch)
 
     def clone(self):
         c = lambda t: None if t is None else t.clone()
-        return LalmState(self.x.clone(), self.g.clone(), self.grad.clone(), self.step, self.l, self.rho,
-                         c(self.x_prev), c(self.grad_prev), self.alpha)
+        s = LalmState(self.x.clone(), self.g.clone(), self.grad.clone(), self.step, self.l, self.rho,
+                      c(self.x_prev), c(self.grad_prev), self.alpha, self.batch)
+        s.l_b, s.rho_b, s.alpha_b = self.l_b.copy(), self.rho_b.copy(), self.alpha_b.copy()
+        return s
 
 
 def lalm_iterate(plan, y, w, denom, beta, delta, state, n_steps, continuation=True,
@@ -295,20 +310,26 @@ def lalm_iterate(plan, y, w, denom, beta, delta, state, n_steps, continuation=Tr
                  stats=None, stream=None, bb=False, bb_alpha_min=0.01):
     """Run ``n_steps`` subset steps; ``state`` (LalmState) is updated in place.
     ``stats``: optional dict of GPU tensors rho (float64), xi (float64),
-    restart (uint8) indexed by global step.  ``forced_restart``: optional
-    uint8 GPU tensor indexed by global step."""
+    restart (uint8) indexed by global step ([batch][capacity] for a batch).
+    ``forced_restart``: optional uint8 GPU tensor indexed by global step
+    ([batch][length] for a batch)."""
     prob = _problem(plan, y, w, denom, beta, delta, nonneg)
-    st = State(_dev(state.x, "x", numel=plan.image_elems), _dev(state.g, "g", numel=plan.image_elems),
-               _dev(state.grad, "grad", numel=plan.image_elems), state.step, state.l, state.rho,
-               _dev(state.x_prev, "x_prev", numel=plan.image_elems, allow_none=True),
-               _dev(state.grad_prev, "grad_prev", numel=plan.image_elems, allow_none=True), state.alpha)
+    nimg = plan.image_elems * plan.B
+    if state.batch != plan.B:
+        raise ValueError("state holds %d images, the plan %d" % (state.batch, plan.B))
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    st = State(_dev(state.x, "x", numel=nimg), _dev(state.g, "g", numel=nimg),
+               _dev(state.grad, "grad", numel=nimg), state.step, state.l, state.rho,
+               _dev(state.x_prev, "x_prev", numel=nimg, allow_none=True),
+               _dev(state.grad_prev, "grad_prev", numel=nimg, allow_none=True), state.alpha,
+               ptr(state.l_b), ptr(state.rho_b), ptr(state.alpha_b))
     fr = _dev(forced_restart, "forced_restart", dtype="uint8", allow_none=True)
     opt = Options(1 if continuation else 0, float(rho_fixed), float(rho_min), int(n_inner), fr,
-                  int(forced_restart.numel()) if forced_restart is not None else 0,
+                  int(forced_restart.numel()) // plan.B if forced_restart is not None else 0,
                   1 if bb else 0, float(bb_alpha_min))
     sp = None
     if stats is not None:
-        cap = min(stats["rho"].numel(), stats["xi"].numel(), stats["restart"].numel())
+        cap = min(stats["rho"].numel(), stats["xi"].numel(), stats["restart"].numel()) // plan.B
         sp = ctypes.byref(Stats(_dev(stats["rho"], "stats.rho", dtype="float64"),
                                 _dev(stats["xi"], "stats.xi", dtype="float64"),
                                 _dev(stats["restart"], "stats.restart", dtype="uint8"), cap))
@@ -320,10 +341,10 @@ def lalm_iterate(plan, y, w, denom, beta, delta, state, n_steps, continuation=Tr
 
 
 def lalm_cost_f64(plan, y, w, beta, delta, x, out, stream=None):
-    """out (float64 GPU tensor, 3 elements) = (Psi, data term, R)."""
+    """out (float64 GPU tensor, 3 elements per image) = (Psi, data term, R)."""
     prob = _problem(plan, y, w, None, beta, delta, True)
-    _check(_lib.lalm_cost_f64(plan.handle, ctypes.byref(prob), _dev(x, "x", numel=plan.image_elems),
-                              _dev(out, "out", dtype="float64", numel=3), _stream(stream)))
+    _check(_lib.lalm_cost_f64(plan.handle, ctypes.byref(prob), _dev(x, "x", numel=plan.image_elems * plan.B),
+                              _dev(out, "out", dtype="float64", numel=3 * plan.B), _stream(stream)))
 
 
 def lalm_dot_f64(plan, a, b, out, stream=None):
@@ -333,9 +354,10 @@ def lalm_dot_f64(plan, a, b, out, stream=None):
 
 
 def lalm_roi_rmsd_f64(plan, a, b, radius_mm, out, stream=None):
-    _check(_lib.lalm_roi_rmsd_f64(plan.handle, _dev(a, "a", numel=plan.image_elems),
-                                  _dev(b, "b", numel=plan.image_elems), float(radius_mm),
-                                  _dev(out, "out", dtype="float64", numel=1), _stream(stream)))
+    """out (float64 GPU tensor, one element per image of the batch)."""
+    n = plan.image_elems * plan.B
+    _check(_lib.lalm_roi_rmsd_f64(plan.handle, _dev(a, "a", numel=n), _dev(b, "b", numel=n), float(radius_mm),
+                                  _dev(out, "out", dtype="float64", numel=plan.B), _stream(stream)))
 
 
 def lalm_profile_begin(plan):

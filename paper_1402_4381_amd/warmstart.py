@@ -147,27 +147,48 @@ class Pipeline:
         return Problem(self.lalm, self.torch, self.plan, y_nat, w_nat, self.dev)
 
     # ---------------------------------------------------------------- pairs
-    def generate_pairs(self, seeds, iters_in, iters_target, pool):
-        torch = self.torch
+    def generate_pairs(self, seeds, iters_in, iters_target, pool, batch=16):
+        """Training pairs (x after iters_in iterations, x after iters_target)
+        for the seeds, ``batch`` scans reconstructed together by one batched
+        plan (every kernel launch covers the batch's images)."""
+        torch, lalm = self.torch, self.lalm
         n = len(seeds)
-        X = torch.empty(n, self.H * self.W, device=self.dev)
-        T = torch.empty(n, self.H * self.W, device=self.dev)
+        npix = self.H * self.W
+        X = torch.empty(n, npix, device=self.dev)
+        T = torch.empty(n, npix, device=self.dev)
+        plan = lalm.lalm_plan_geometry(self.synth.geometry_of(self.cfg), self.M, batch=batch)
+        vos = torch.as_tensor(plan.view_of_slot, dtype=torch.long, device=self.dev)
+        sino = plan.sino_elems
+        Y = torch.zeros(batch, sino, device=self.dev)
+        Wt = torch.zeros(batch, sino, device=self.dev)
+        D = torch.empty(batch * npix, device=self.dev)
         t0 = time.perf_counter()
         gpu_s = 0.0
-        for k, (seed, y, w) in enumerate(pool.imap(_worker_sino, seeds, chunksize=1)):
+        it = pool.imap(_worker_sino, seeds, chunksize=1)
+        for k0 in range(0, n, batch):
+            nb = min(batch, n - k0)
+            for b in range(nb):
+                _, y, w = next(it)
+                Y[b].copy_(torch.as_tensor(y, device=self.dev).index_select(0, vos).reshape(-1))
+                Wt[b].copy_(torch.as_tensor(w, device=self.dev).index_select(0, vos).reshape(-1))
+            # a short last batch repeats its first scan in the unused images
+            for b in range(nb, batch):
+                Y[b].copy_(Y[0])
+                Wt[b].copy_(Wt[0])
             g0 = time.perf_counter()
-            prob = self.problem(y, w)
-            st = self.zero_state()
-            self.iterate(prob, st, iters_in)
-            X[k].copy_(st.x)
-            self.iterate(prob, st, iters_target - iters_in)
-            T[k].copy_(st.x)
+            lalm.lalm_sqs_denom(plan, Wt, D)
+            st = lalm.LalmState.zeros_like(torch.zeros(batch * npix, device=self.dev), batch=batch)
+            lalm.lalm_iterate(plan, Y, Wt, D, self.beta, self.delta, st, iters_in * self.M, n_inner=self.n_inner)
+            X[k0:k0 + nb].copy_(st.x.view(batch, npix)[:nb])
+            lalm.lalm_iterate(plan, Y, Wt, D, self.beta, self.delta, st, (iters_target - iters_in) * self.M,
+                              n_inner=self.n_inner)
+            T[k0:k0 + nb].copy_(st.x.view(batch, npix)[:nb])
             torch.cuda.synchronize()
             gpu_s += time.perf_counter() - g0
-            if (k + 1) % max(1, n // 20) == 0 or k + 1 == n:
-                print("pairs %d/%d  %.1f s (GPU %.1f s)" % (k + 1, n, time.perf_counter() - t0, gpu_s),
+            if (k0 // batch + 1) % max(1, n // batch // 20) == 0 or k0 + nb == n:
+                print("pairs %d/%d  %.1f s (GPU %.1f s)" % (k0 + nb, n, time.perf_counter() - t0, gpu_s),
                       flush=True)
-        return X, T, dict(n=n, wall_s=round(time.perf_counter() - t0, 2), gpu_s=round(gpu_s, 2))
+        return X, T, dict(n=n, batch=batch, wall_s=round(time.perf_counter() - t0, 2), gpu_s=round(gpu_s, 2))
 
     # ------------------------------------------------------------- training
     def train(self, X, T, epochs, batch, lr, seed=0, params=None, log_every=50):
@@ -524,6 +545,7 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=14)
     ap.add_argument("--weights", default=WEIGHTS, help="weights file to write (train) or read (eval only)")
     ap.add_argument("--eval-only", action="store_true")
+    ap.add_argument("--pair-batch", type=int, default=16, help="scans reconstructed together for the pairs")
     ap.add_argument("--n-inner", type=int, default=1,
                     help="inner FISTA iterations per subset step of the plain and warm-started runs")
     ap.add_argument("--volume", default=None,
@@ -560,7 +582,7 @@ def main(argv=None):
     else:
         lo, hi = ws["train_seeds"]
         seeds = list(range(lo, min(hi, lo + args.pairs)))
-        X, T, info = pipe.generate_pairs(seeds, ws["iters_in"], ws["iters_target"], pool)
+        X, T, info = pipe.generate_pairs(seeds, ws["iters_in"], ws["iters_target"], pool, batch=args.pair_batch)
         pool.close()
         pool.join()
         report["pairs"] = info

@@ -68,16 +68,24 @@ def _geom(**kw):
 def test_invalid_geometry_rejected_before_gpu_work(lib, kw, M):
     from paper_1402_4381_amd import lalm
     h = ctypes.c_void_p()
-    st = lalm._lib.lalm_plan_geometry(ctypes.byref(_geom(**kw)), M, ctypes.byref(h))
+    st = lalm._lib.lalm_plan_geometry(ctypes.byref(_geom(**kw)), M, 1, ctypes.byref(h))
     assert st == lalm.LALM_E_INVALID
     assert h.value is None
     assert len(lalm.lalm_last_error()) > 0
 
 
+@pytest.mark.parametrize("batch", [0, -1, 65536])
+def test_invalid_batch_rejected(lib, batch):
+    from paper_1402_4381_amd import lalm
+    h = ctypes.c_void_p()
+    assert lalm._lib.lalm_plan_geometry(ctypes.byref(_geom()), 4, batch, ctypes.byref(h)) == lalm.LALM_E_INVALID
+    assert h.value is None and "batch" in lalm.lalm_last_error()
+
+
 def test_null_arguments_rejected(lib):
     from paper_1402_4381_amd import lalm
     L = lalm._lib
-    assert L.lalm_plan_geometry(None, 4, None) == lalm.LALM_E_INVALID
+    assert L.lalm_plan_geometry(None, 4, 1, None) == lalm.LALM_E_INVALID
     assert L.lalm_plan_info(None, None, None, None, None, None, None) == lalm.LALM_E_INVALID
     assert L.lalm_project_subset(None, 0, None, None, None, None, None) == lalm.LALM_E_INVALID
     assert L.lalm_backproject_subset(None, 0, None, None, 1.0, 0, None) == lalm.LALM_E_INVALID
