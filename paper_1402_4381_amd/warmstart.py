@@ -255,6 +255,31 @@ class Pipeline:
         return dict(batch=batch, ms=round(dt * 1e3, 4), gflop=round(fl / 1e9, 2),
                     tflops=round(fl / dt / 1e12, 1), frac_bf16_peak=round(fl / dt / 2.5e15, 4))
 
+    def train_step_time(self, params, batch=8, reps=20):
+        """Wall time of one training step (loss, gradient, Adam) on a
+        synthetic batch, and its rate at 3x the forward FLOPs."""
+        torch, lalm = self.torch, self.lalm
+        net = lalm.lalm_unet_create(batch, self.H, self.W)
+        P = lalm.lalm_unet_param_count()
+        p = params.clone()
+        m, v, grad = (torch.zeros(P, device=self.dev) for _ in range(3))
+        loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        x = torch.rand(batch * self.H * self.W, device=self.dev) * 0.02
+        t = x + 1e-4 * torch.rand_like(x)
+        for k in range(3):
+            lalm.lalm_unet_loss_grad(net, p, x, t, self.mask, self.hu, batch, grad, loss, in_scale=self.in_scale)
+            lalm.lalm_unet_adam(net, p, grad, m, v, k + 1, 1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(reps):
+            lalm.lalm_unet_loss_grad(net, p, x, t, self.mask, self.hu, batch, grad, loss, in_scale=self.in_scale)
+            lalm.lalm_unet_adam(net, p, grad, m, v, k + 4, 1e-4)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        fl = 3.0 * forward_flops(self.H, self.W) * batch
+        return dict(batch=batch, ms=round(dt * 1e3, 4), tflops=round(fl / dt / 1e12, 1),
+                    frac_bf16_peak=round(fl / dt / 2.5e15, 4))
+
     def warm_start(self, prob, params, net, iters_in, out=None):
         """iters_in plain iterations, U-Net, cost guard, state reset.
         Returns (state, kept, psi_in, psi_net, network image)."""
@@ -551,6 +576,8 @@ def main(argv=None):
     ap.add_argument("--volume", default=None,
                     help="3D workload: per-slice warm start with the committed weights (no training)")
     ap.add_argument("--out", default=None, help="JSON summary path")
+    ap.add_argument("--unet-timing", action="store_true",
+                    help="only time the network: forward at batch 1 and 8, a training step at batch 8")
     args = ap.parse_args(argv)
 
     import multiprocessing as mp
@@ -570,12 +597,17 @@ def main(argv=None):
         raise SystemExit("the warm start is 2D (one network per slice image)")
     ws = dict(synth.configs.UNET_WARMSTART)
     pool = None
-    if not args.eval_only:
+    if not args.eval_only and not args.unet_timing:
         # CPU workers are forked before the GPU is touched
         pool = mp.get_context("fork").Pool(args.workers, initializer=_worker_init, initargs=(cfg,))
 
     pipe = Pipeline(cfg, n_inner=args.n_inner)
     torch = pipe.torch
+    if args.unet_timing:
+        params = torch.as_tensor(np.load(args.weights), device=pipe.dev).contiguous()
+        res = dict(forward=[pipe.unet_time(params, b) for b in (1, 8)], train=pipe.train_step_time(params, 8))
+        print(json.dumps(res), flush=True)
+        return res
     report = dict(workload=args.workload, warmstart=ws, n_inner=args.n_inner)
     if args.eval_only:
         params = torch.as_tensor(np.load(args.weights), device=pipe.dev).contiguous()
