@@ -306,6 +306,18 @@ LALM_API lalm_status lalm_cost_f64(lalm_plan *plan, const lalm_problem *prob, co
 /* out_dev[0] = sum_i a_i b_i over n elements (for the adjoint test). */
 LALM_API lalm_status lalm_dot_f64(lalm_plan *plan, const float *a, const float *b, int64_t n,
                          double *out_dev, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same
+ * out_dev[0] = sum_i a_i b_i as lalm_dot_f64, with the same kernels and
+ * bits, without a plan.  Its scratch, 1024 FP64 block partials (8 KiB), is
+ * a file-scope device array of the library, one per GPU, held until the
+ * process ends; the call allocates nothing.  Calls that overlap on one GPU
+ * (concurrent streams, threads) share that array and race: serialize them.
+ * Errors: LALM_E_INVALID for null pointers, n < 0 or n > 2^40; LALM_E_HIP
+ * when the scratch address or a launch fails. */
+LALM_API lalm_status lalm_dot_f64_noalloc(const float *a, const float *b, int64_t n, double *out_dev,
+                                          hipStream_t stream);
 /* out_dev[0] = RMS of (a - b) over voxels whose centre lies within radius_mm
  * of the rotation axis, all slices (Sec. V: RMS difference in the ROI);
  * with a batch out_dev[b] for image b. */

@@ -2,6 +2,8 @@
 // forward projector, regularizer value here), inner products for the adjoint
 // test and the ROI RMS difference.  Every reduction uses a fixed grid and a
 // fixed summation order, so results are bit-reproducible.
+#include <mutex>
+
 #include "lalm_internal.h"
 
 namespace lalm {
@@ -168,3 +170,71 @@ hipError_t launch_combine_cost(double *out3, const double *data, const double *r
 }
 
 }  // namespace lalm
+
+// ------------------------------------------------------------ no allocation
+//
+// lalm_dot_f64_noalloc: the dot product of lalm_dot_f64 for callers that
+// cannot allocate device memory (code under graph capture, tight serving
+// loops).  Its only scratch, the FP64 block partials, lives in a file-scope
+// device array: one per GPU, held until the process ends, shared by every
+// call on that GPU.  The host reaches it through the address
+// hipGetSymbolAddress returns for the current device, never through the
+// array's name.
+
+static __device__ __align__(256) double scratch[lalm::kRedBlocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr int64_t kNoallocMaxN = int64_t(1) << 40;    // elements per operand
+double *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// This device's copy of the scratch array (looked up once per device).
+hipError_t scratch_of_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" lalm_status lalm_dot_f64_noalloc(const float *a, const float *b, int64_t n, double *out_dev,
+                                            hipStream_t st)
+{
+    if (!a || !b || !out_dev || n < 0) {
+        lalm::set_error("lalm_dot_f64_noalloc: bad argument");
+        return LALM_E_INVALID;
+    }
+    if (n > kNoallocMaxN) {
+        lalm::set_error("lalm_dot_f64_noalloc: more than 2^40 elements");
+        return LALM_E_INVALID;
+    }
+    double *part = nullptr;
+    hipError_t e = scratch_of_current_device(&part);
+    if (e != hipSuccess) {
+        lalm::set_error(std::string("lalm_dot_f64_noalloc: scratch address: ") + hipGetErrorString(e));
+        return LALM_E_HIP;
+    }
+    // the same kernels and grid as lalm_dot_f64: every block overwrites its
+    // partial, so nothing needs clearing between calls
+    hipLaunchKernelGGL(lalm::dot_kernel, dim3(lalm::kRedBlocks), dim3(256), 0, st, a, b, (long long)n, part);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = lalm::launch_sum_partials(part, lalm::kRedBlocks, out_dev, 1.0, st);
+    if (e != hipSuccess) {
+        lalm::set_error(std::string("lalm_dot_f64_noalloc: ") + hipGetErrorString(e));
+        return LALM_E_HIP;
+    }
+    return LALM_OK;
+}

@@ -25,7 +25,7 @@ EXPORTS = ("lalm_last_error", "lalm_version", "lalm_plan_geometry", "lalm_plan_i
            "lalm_roi_rmsd_f64", "lalm_profile_begin", "lalm_profile_read",
            "lalm_profile_end", "lalm_unet_param_count", "lalm_unet_create",
            "lalm_unet_destroy", "lalm_unet_forward", "lalm_unet_loss_grad", "lalm_unet_adam",
-           "lalm_unet_capture_elems", "lalm_unet_capture")
+           "lalm_unet_capture_elems", "lalm_unet_capture", "lalm_dot_f64_noalloc")
 
 
 class LalmError(RuntimeError):
@@ -89,6 +89,7 @@ def _load():
                           ctypes.POINTER(Options), ctypes.POINTER(Stats), P], I32),
         "lalm_cost_f64": ([P, ctypes.POINTER(Problem), P, P, P], I32),
         "lalm_dot_f64": ([P, P, P, I64, P, P], I32),
+        "lalm_dot_f64_noalloc": ([P, P, I64, P, P], I32),
         "lalm_roi_rmsd_f64": ([P, P, P, F64, P, P], I32),
         "lalm_profile_begin": ([P], I32),
         "lalm_profile_read": ([P, P, P], I32),
@@ -351,6 +352,14 @@ def lalm_dot_f64(plan, a, b, out, stream=None):
     n = min(a.numel(), b.numel())
     _check(_lib.lalm_dot_f64(plan.handle, _dev(a, "a"), _dev(b, "b"), int(n),
                              _dev(out, "out", dtype="float64", numel=1), _stream(stream)))
+
+
+def lalm_dot_f64_noalloc(a, b, out, stream=None):
+    """lalm_dot_f64 without a plan and without allocation (the library's
+    per-GPU static scratch; calls overlapping on one GPU race)."""
+    n = min(a.numel(), b.numel())
+    _check(_lib.lalm_dot_f64_noalloc(_dev(a, "a"), _dev(b, "b"), int(n),
+                                     _dev(out, "out", dtype="float64", numel=1), _stream(stream)))
 
 
 def lalm_roi_rmsd_f64(plan, a, b, radius_mm, out, stream=None):
