@@ -269,14 +269,18 @@ __device__ inline void store_b(bf16 *Bs, int tid, const bf16x8 *rb)
     }
 }
 
-template <int AMODE, int BMODE, int EPI, int BM, int BN>
+// Four waves; each owns WMT x WNT accumulators of 32 x 32 (a 32 WMT x 32 WNT
+// block of C), so one LDS stage feeds 2 WMT WNT independent MFMAs per wave.
+template <int AMODE, int BMODE, int EPI, int BM, int BN, int WMT, int WNT>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
-    static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32x32");
-    __shared__ __attribute__((aligned(16))) bf16 As[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * LDK];
+    constexpr int NWM = BM / (32 * WMT), NWN = BN / (32 * WNT);
+    static_assert(NWM * NWN == 4, "four waves");
+    static_assert(BM * (BN + 8) <= 2 * (BM + BN) * LDK, "epilogue staging fits in the operand buffers");
+    __shared__ __attribute__((aligned(16))) bf16 smem[2 * (BM + BN) * LDK];
+    // A stages at smem + buf BM LDK, B stages after both A stages
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wm = wv % (BM / 32), wn = wv / (BM / 32);
+    const int wm = wv % NWM, wn = wv / NWM;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     int kbeg = 0, kend = g.K;
     if (EPI == E_WG) {
@@ -288,9 +292,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     bf16x8 ra[NVA], rb[NVB];
     ARow rs[NVA];
     if (AMODE != A_MC) init_rows<AMODE, BM>(g, m0, tid, rs);
-    floatx16 acc;
+    floatx16 acc[WMT][WNT];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    for (int a = 0; a < WMT; ++a)
+#pragma unroll
+        for (int b = 0; b < WNT; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
     int buf = 0;
     if (kbeg < kend) {
@@ -298,37 +306,51 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
         load_b<BMODE, BN>(g, n0, kbeg, tid, rb);
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        store_a<AMODE, BM>(As[buf], tid, ra);
-        store_b<BMODE, BN>(Bs[buf], tid, rb);
+        bf16 *as_buf = smem + buf * (BM * LDK), *bs_buf = smem + 2 * BM * LDK + buf * (BN * LDK);
+        store_a<AMODE, BM>(as_buf, tid, ra);
+        store_b<BMODE, BN>(bs_buf, tid, rb);
         __syncthreads();
         if (k0 + BK < kend) {                      // prefetch the next tile
             load_a<AMODE, BM>(g, rs, m0, k0 + BK, tid, ra);
             load_b<BMODE, BN>(g, n0, k0 + BK, tid, rb);
         }
-        const bf16 *as = As[buf] + (wm * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
-        const bf16 *bs = Bs[buf] + (wn * 32 + (lane & 31)) * LDK + 8 * (lane >> 5);
+        const bf16 *as = as_buf + (wm * 32 * WMT + (lane & 31)) * LDK + 8 * (lane >> 5);
+        const bf16 *bs = bs_buf + (wn * 32 * WNT + (lane & 31)) * LDK + 8 * (lane >> 5);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(as + kk);
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(bs + kk);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            bf16x8 a[WMT], b[WNT];
+#pragma unroll
+            for (int i = 0; i < WMT; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(as + i * 32 * LDK + kk);
+#pragma unroll
+            for (int j = 0; j < WNT; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(bs + j * 32 * LDK + kk);
+#pragma unroll
+            for (int i = 0; i < WMT; ++i)
+#pragma unroll
+                for (int j = 0; j < WNT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         buf ^= 1;
     }
 
-    // element t of acc: row wm*32 + 8(t/4) + 4(lane/32) + t%4, column wn*32 + lane%32
-    const int col = n0 + wn * 32 + (lane & 31);
+    // element t of acc[i][j]: row wm*32*WMT + 32 i + 8(t/4) + 4(lane/32) + t%4,
+    // column wn*32*WNT + 32 j + lane%32
     if (EPI == E_FWD) {
         __syncthreads();
-        bf16 *Cs = As[0];                          // BM x (BN + 8) bf16 staging (fits in 2*BM*LDK)
+        bf16 *Cs = smem;                           // BM x (BN + 8) bf16 staging
         constexpr int LDC = BN + 8;
-        const float bv = (col < g.N && g.bias) ? g.bias[g.yup == 2 ? col % g.yc : col] : 0.0f;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int r = wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
-            float v = acc[t] + bv;
-            if (g.relu) v = fmaxf(v, 0.0f);
-            Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
+        for (int j = 0; j < WNT; ++j) {
+            const int cl = wn * 32 * WNT + 32 * j + (lane & 31), col = n0 + cl;
+            const float bv = (col < g.N && g.bias) ? g.bias[g.yup == 2 ? col % g.yc : col] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < WMT; ++i)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int r = wm * 32 * WMT + 32 * i + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+                    float v = acc[i][j][t] + bv;
+                    if (g.relu) v = fmaxf(v, 0.0f);
+                    Cs[r * LDC + cl] = (bf16)v;
+                }
         }
         __syncthreads();
         for (int s = tid; s < BM * (BN / 8); s += 256) {
@@ -349,22 +371,25 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
             }
             *reinterpret_cast<bf16x8 *>(g.y + pix * ldy + c) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
         }
-    } else if (EPI == E_DG) {
-        if (col >= g.N) return;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int m = m0 + wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
-            if (m >= g.M) continue;
-            if (col < g.oc1) g.o1[(long long)m * g.oc1 + col] = acc[t];
-            else g.o2[(long long)m * (g.N - g.oc1) + (col - g.oc1)] = acc[t];
-        }
     } else {
-        if (col >= g.N) return;
-        float *dst = g.part + (long long)blockIdx.z * g.M * g.N;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int m = m0 + wm * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
-            if (m < g.M) dst[(long long)m * g.N + col] = acc[t];
+        for (int j = 0; j < WNT; ++j) {
+            const int col = n0 + wn * 32 * WNT + 32 * j + (lane & 31);
+            if (col >= g.N) continue;
+            float *dst = EPI == E_WG ? g.part + (long long)blockIdx.z * g.M * g.N : nullptr;
+#pragma unroll
+            for (int i = 0; i < WMT; ++i)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int m = m0 + wm * 32 * WMT + 32 * i + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+                    if (m >= g.M) continue;
+                    if (EPI == E_DG) {
+                        if (col < g.oc1) g.o1[(long long)m * g.oc1 + col] = acc[i][j][t];
+                        else g.o2[(long long)m * (g.N - g.oc1) + (col - g.oc1)] = acc[i][j][t];
+                    } else {
+                        dst[(long long)m * g.N + col] = acc[i][j][t];
+                    }
+                }
         }
     }
 }
@@ -482,12 +507,16 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g)
 template <int AMODE, int BMODE, int EPI>
 hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
 {
+    // wide tiles, four accumulators per wave, wherever N fills them
     if (g.N <= 32) {
         dim3 grd((g.M + 127) / 128, (g.N + 31) / 32, nsplit);
-        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 128, 32>), grd, dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 128, 32, 1, 1>), grd, dim3(256), 0, st, g);
+    } else if (g.N <= 64) {
+        dim3 grd((g.M + 255) / 256, (g.N + 63) / 64, nsplit);
+        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 256, 64, 2, 2>), grd, dim3(256), 0, st, g);
     } else {
-        dim3 grd((g.M + 63) / 64, (g.N + 63) / 64, nsplit);
-        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 64, 64>), grd, dim3(256), 0, st, g);
+        dim3 grd((g.M + 127) / 128, (g.N + 127) / 128, nsplit);
+        hipLaunchKernelGGL((gemm_kernel<AMODE, BMODE, EPI, 128, 128, 2, 2>), grd, dim3(256), 0, st, g);
     }
     return hipGetLastError();
 }
