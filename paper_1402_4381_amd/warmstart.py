@@ -576,6 +576,8 @@ def main(argv=None):
     ap.add_argument("--volume", default=None,
                     help="3D workload: per-slice warm start with the committed weights (no training)")
     ap.add_argument("--out", default=None, help="JSON summary path")
+    ap.add_argument("--pairs-only", action="store_true",
+                    help="only generate the training pairs and report their timing")
     ap.add_argument("--unet-timing", action="store_true",
                     help="only time the network: forward at batch 1 and 8, a training step at batch 8")
     args = ap.parse_args(argv)
@@ -618,6 +620,9 @@ def main(argv=None):
         pool.close()
         pool.join()
         report["pairs"] = info
+        if args.pairs_only:
+            print(json.dumps(report), flush=True)
+            return report
         params, tinfo = pipe.train(X, T, args.epochs, args.batch, args.lr)
         report["train"] = tinfo
         del X, T
