@@ -502,6 +502,40 @@ def time_to_1hu_volume(lalm, torch, synth, cfg, data, plan, y, w, denom, beta, d
     return res
 
 
+def batched_throughput(lalm, torch, np, synth, cfg, data, beta, delta, B, steps, dev):
+    """Subset iterations per second summed over B independent scans of the
+    workload reconstructed by one batched plan (every launch covers the B
+    images), and the per-image kernel times; the scans are the workload's
+    data with a different noise realization each."""
+    M = cfg["M"]
+    plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), M, batch=B)
+    vos = torch.as_tensor(plan.view_of_slot, dtype=torch.long, device=dev)
+    ys, ws = [], []
+    for b in range(B):
+        y_, w_ = synth.noisy_data(cfg, data["ybar"], 9000 + b)
+        ys.append(torch.as_tensor(y_.astype("float32"), device=dev).index_select(0, vos).reshape(-1))
+        ws.append(torch.as_tensor(w_.astype("float32"), device=dev).index_select(0, vos).reshape(-1))
+    y, w = torch.cat(ys), torch.cat(ws)
+    denom = torch.empty(B * plan.image_elems, device=dev)
+    lalm.lalm_sqs_denom(plan, w, denom)
+    st = lalm.LalmState.zeros_like(torch.zeros(B * plan.image_elems, device=dev), batch=B)
+    lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, 2 * M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lalm.lalm_profile_begin(plan)
+    lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, steps)
+    ms, cnt = lalm.lalm_profile_read(plan)
+    lalm.lalm_profile_end(plan)
+    avg_us = ms / np.maximum(cnt, 1) * 1e3
+    return dict(images=B, steps=steps, value=round(B * steps / dt, 2), unit="image subset_iters/s",
+                ms_per_step=round(dt / steps * 1e3, 5),
+                kernels_avg_us_per_launch={k: round(float(v), 3) for k, v in zip(("update", "project", "backproject"),
+                                                                                  avg_us)})
+
+
 def fan2d_figures(lalm, torch, np, synth, steps, warmup, dev, with_1hu):
     """Throughput, roofline and time to 1 HU of the 512^2 fan-beam workload."""
     cfg = synth.get_config("fan2d_512")
@@ -510,6 +544,7 @@ def fan2d_figures(lalm, torch, np, synth, steps, warmup, dev, with_1hu):
     delta = synth.configs.delta_mu(cfg)
     rec, _ = throughput(lalm, torch, np, cfg, plan, y, w, denom, beta, delta, steps, warmup, dev)
     rec.update(steps=steps, warmup=warmup, workload="fan2d_512", subsets=cfg["M"])
+    rec["batch_16"] = batched_throughput(lalm, torch, np, synth, cfg, data, beta, delta, 16, steps // 4, dev)
     if with_1hu:
         log("bench: fan2d_512 x* and wall time to 1 HU")
         rec["time_to_1hu"] = time_to_1hu_2d(lalm, torch, synth, cfg, data, plan, y, w, denom, beta, delta, dev,

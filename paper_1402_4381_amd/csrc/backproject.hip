@@ -542,6 +542,7 @@ struct Step2dArgs {
     float scale, beta, inv_delta2;
     double rho_min;
     int continuation, nonneg;
+    int tiles_x, tiles_y;   // 32 x 32 tiles; partial of tile (bx, by) at bx + tiles_x by
     BatchStr bs;            // image b = blockIdx.z
 };
 
@@ -572,9 +573,18 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
         A.sc += bi;
         A.partials += bi * A.bs.part;
     }
+    // tile of this block: the hardware hands consecutive blocks to the eight
+    // XCDs in turn; XCD c takes the c-th eighth of the tiles in column-major
+    // order (a strip of whole tile columns), so the left and right halo
+    // lines of the neighbourhood loads are shared inside one XCD's L2.  The
+    // grid is padded to a multiple of 8; padding blocks have no tile.
+    const int ntile = A.tiles_x * A.tiles_y;
+    const int tl = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+    if (tl >= ntile) return;
+    const int bx = tl / A.tiles_y, by = tl - bx * A.tiles_y;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + 32 * ty;
-    const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
+    const int i = bx * 32 + tx, j = by * 32 + ty;
     const bool inside = i < K.nx && j < K.ny;
     const long long idx = (long long)j * K.nx + i;
     // the scalar record and the loads that do not depend on it go out
@@ -636,10 +646,10 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
         double t = s_red[0];
 #pragma unroll
         for (int w = 1; w < 16; ++w) t += s_red[w];
-        A.partials[blockIdx.x + gridDim.x * blockIdx.y] = t;
+        A.partials[bx + A.tiles_x * by] = t;
     }
     if (LAST) return;
-    const int it = blockIdx.x * 32 + ty, jt = blockIdx.y * 32 + tx;
+    const int it = bx * 32 + ty, jt = by * 32 + tx;
     if (it < K.nx && jt < K.ny) {
         const long long t_idx = (long long)it * K.ldT + jt + 2;
         A.XT0[t_idx] = tile[0][tx][ty];
@@ -791,8 +801,11 @@ hipError_t launch_step2d(const lalm_plan *p, const float *xs0, const float *xs1,
     a.continuation = e.cont.continuation;
     a.nonneg = nonneg;
     a.bs = batch_str(p);
-    const dim3 grd((p->nx + 31) / 32, (p->ny + 31) / 32, p->B);
-    p->bp_nblocks = (long long)grd.x * grd.y;
+    a.tiles_x = (p->nx + 31) / 32;
+    a.tiles_y = (p->ny + 31) / 32;
+    const int ntile = a.tiles_x * a.tiles_y;
+    const dim3 grd((unsigned)((ntile + 7) / 8 * 8), 1, p->B);   // padded to the eight XCDs
+    p->bp_nblocks = ntile;
     return last ? klaunch(p, step2d_kernel<true>, grd, dim3(32, 32), st, a)
                 : klaunch(p, step2d_kernel<false>, grd, dim3(32, 32), st, a);
 }

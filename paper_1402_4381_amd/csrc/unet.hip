@@ -397,62 +397,114 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 // ------------------------------------------------------------------------
 // 3x3 convolution (forward, or the input gradient with mirrored taps) as an
 // implicit GEMM whose input tile is staged once per chunk of 32 channels.
-// A block owns a TH x 16 pixel tile of one image and BN output channels.  For
-// each chunk it loads the (TH + 2) x 18 pixel patch (zero outside the image)
-// and the BN x 9 x 32 weights into LDS; every wave then runs 9 taps x 2 MFMA
-// k-steps reading its operands from LDS, so the nine taps re-read the patch
-// in LDS instead of memory.  Same MFMA, operand layouts and epilogues as
-// gemm_kernel (E_FWD: bias, ReLU, bf16 NHWC; E_DG: FP32 split output).
+// A block owns BN output channels and a run of consecutive TH x 16 pixel
+// tiles.  The BN x 9 x cin weights (cin = 32 NCH) go to LDS once; then for
+// each (tile, chunk of 32 input channels) it stores the (TH + 2) x 18 pixel
+// patch (zero outside the image), already in registers, to LDS, issues the
+// loads of the next patch, and every wave runs 9 taps x 2 MFMA k-steps
+// reading its operands from LDS, so the nine taps re-read the patch in LDS
+// instead of memory and the next patch is in flight meanwhile.  Same MFMA,
+// operand layouts and epilogues as gemm_kernel (E_FWD: bias, ReLU, bf16
+// NHWC; E_DG: FP32 split output).
 constexpr int CV_TW = 16;              // tile width (pixels)
 constexpr int CV_LDP = 40;             // LDS stride per patch pixel / weight tap (bf16): 32 + 8
 constexpr int CV_LDW = 9 * CV_LDP;     // LDS stride per weight row (9 taps)
 
-template <int EPI, int BM, int BN>
-__global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g)
+template <int EPI, int BM, int BN, int NCH>
+__global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_block)
 {
     static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32x32");
-    static_assert(BM * (BN + 8) <= BN * CV_LDW, "epilogue staging fits in the weight buffer");
     constexpr int TH = BM / CV_TW;                 // tile rows
     constexpr int PH = TH + 2, PW = CV_TW + 2;     // patch with a one-pixel halo
+    constexpr int NPV = PH * PW * 4;               // patch vectors of 8 channels
+    constexpr int NP = (NPV + 255) / 256;          // per thread
+    constexpr int NWV = NCH * BN * 36;             // weight vectors
+    constexpr int NW = (NWV + 255) / 256;
+    constexpr int LDC = BN + 8;
     __shared__ __attribute__((aligned(16))) bf16 Ps[PH * PW * CV_LDP];
-    __shared__ __attribute__((aligned(16))) bf16 Ws[BN * CV_LDW];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[NCH * BN * CV_LDW];
+    __shared__ __attribute__((aligned(16))) bf16 Cs[EPI == E_FWD ? BM * LDC : 8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv % (BM / 32), wn = wv / (BM / 32);
     const int ntx = (g.gW + CV_TW - 1) / CV_TW, nty = (g.gH + TH - 1) / TH;
-    int t = blockIdx.x;
-    const int tx0 = (t % ntx) * CV_TW;
-    t /= ntx;
-    const int ty0 = (t % nty) * TH;
-    const int b = t / nty;
+    const int ntiles = g.gB * nty * ntx;
+    int t = blockIdx.x * tiles_per_block;
+    const int tend = min(ntiles, t + tiles_per_block);
+    if (t >= tend) return;
     const int n0 = blockIdx.y * BN;
-    const int cin = g.ac1 + g.ac2;
-    floatx16 acc;
+    const int cin = g.ac1 + g.ac2;                 // 32 NCH
+
+    // the patch of (tile tt, chunk cc) -> registers, one vector per slot
+    auto load_patch = [&](int tt, int cc, bf16x8 *rp) {
+        const int tx0 = (tt % ntx) * CV_TW;
+        const int rest = tt / ntx;
+        const int ty0 = (rest % nty) * TH, b = rest / nty;
+        const bool first = 32 * cc < g.ac1;        // 32 divides both channel counts
+        const bf16 *src = first ? g.a1 : g.a2;
+        const int cs = first ? g.ac1 : g.ac2, c0 = first ? 32 * cc : 32 * cc - g.ac1;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+        for (int v = 0; v < NP; ++v) {
+            const int sl = tid + v * 256;
+            const int q = sl & 3, pp = sl >> 2;
+            const int yy = ty0 + pp / PW - 1, xx = tx0 + pp % PW - 1;
+            bf16x8 val = zero8();
+            if ((NPV % 256 == 0 || sl < NPV) && (unsigned)yy < (unsigned)g.gH && (unsigned)xx < (unsigned)g.gW)
+                val = ld8(src + (((long long)b * g.gH + yy) * g.gW + xx) * cs + c0 + 8 * q);
+            rp[v] = val;
+        }
+    };
+
+    bf16x8 rp[NP];
+    load_patch(t, 0, rp);
+    {
+        // all weights, [chunk][N][tap][32 channels], rows from K = tap * cin + c
+        bf16x8 rw[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            const int sl = tid + v * 256;
+            const int q = sl & 3, tp = (sl >> 2) % 9, row = sl / 36;   // row = chunk * BN + nn
+            const int cc = row / BN, nn = row - cc * BN;
+            bf16x8 val = zero8();
+            if ((NWV % 256 == 0 || sl < NWV) && n0 + nn < g.N)
+                val = ld8(g.w + (long long)(n0 + nn) * g.K + tp * cin + 32 * cc + 8 * q);
+            rw[v] = val;
+        }
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            const int sl = tid + v * 256;
+            if (NWV % 256 != 0 && sl >= NWV) continue;
+            const int q = sl & 3, tp = (sl >> 2) % 9, row = sl / 36;
+            *reinterpret_cast<bf16x8 *>(Ws + row * CV_LDW + tp * CV_LDP + 8 * q) = rw[v];
+        }
+    }
+
     // this lane's A row: tile pixel wm*32 + lane%32 (row-major TH x 16)
     const int pr = wm * 32 + (lane & 31);
     const int py = pr / CV_TW, px = pr % CV_TW;
-    for (int c0 = 0; c0 < cin; c0 += 32) {
-        const bool first = c0 < g.ac1;             // 32 divides both channel counts
-        const bf16 *src = first ? g.a1 : g.a2;
-        const int cs = first ? g.ac1 : g.ac2, cc = first ? c0 : c0 - g.ac1;
-        __syncthreads();                           // the previous chunk's readers are done
-        for (int s = tid; s < PH * PW * 4; s += 256) {
-            const int v = s & 3, pp = s >> 2;
-            const int yy = ty0 + pp / PW - 1, xx = tx0 + pp % PW - 1;
-            bf16x8 val = zero8();
-            if ((unsigned)yy < (unsigned)g.gH && (unsigned)xx < (unsigned)g.gW)
-                val = ld8(src + (((long long)b * g.gH + yy) * g.gW + xx) * cs + cc + 8 * v);
-            *reinterpret_cast<bf16x8 *>(Ps + pp * CV_LDP + 8 * v) = val;
-        }
-        for (int s = tid; s < BN * 36; s += 256) {  // [N][K] rows, K = tap * cin + c
-            const int v = s & 3, tp = (s >> 2) % 9, nn = s / 36;
-            bf16x8 val = zero8();
-            if (n0 + nn < g.N) val = ld8(g.w + (long long)(n0 + nn) * g.K + tp * cin + c0 + 8 * v);
-            *reinterpret_cast<bf16x8 *>(Ws + nn * CV_LDW + tp * CV_LDP + 8 * v) = val;
+    const int col = n0 + wn * 32 + (lane & 31);
+    float bv = 0.0f;
+    if (EPI == E_FWD) bv = (col < g.N && g.bias) ? g.bias[col] : 0.0f;
+    floatx16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    int c = 0;
+    for (;;) {
+        __syncthreads();                           // the previous item's readers are done
+#pragma unroll
+        for (int v = 0; v < NP; ++v) {
+            const int sl = tid + v * 256;
+            if (NPV % 256 != 0 && sl >= NPV) continue;
+            *reinterpret_cast<bf16x8 *>(Ps + (sl >> 2) * CV_LDP + 8 * (sl & 3)) = rp[v];
         }
         __syncthreads();
-        const bf16 *ws = Ws + (wn * 32 + (lane & 31)) * CV_LDW + 8 * (lane >> 5);
+        int tn = t, cn = c + 1;
+        if (cn == NCH) {
+            cn = 0;
+            ++tn;
+        }
+        const bool more = tn < tend;
+        if (more) load_patch(tn, cn, rp);          // in flight during the MFMAs
+        const bf16 *ws = Ws + (c * BN + wn * 32 + (lane & 31)) * CV_LDW + 8 * (lane >> 5);
 #pragma unroll
         for (int tp = 0; tp < 9; ++tp) {
             const int dy = g.tsign * (tp / 3 - 1), dx = g.tsign * (tp % 3 - 1);
@@ -464,45 +516,49 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g)
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc, 0, 0, 0);
             }
         }
-    }
-
-    // element t of acc: tile pixel wm*32 + 8(t/4) + 4(lane/32) + t%4, column wn*32 + lane%32
-    const int col = n0 + wn * 32 + (lane & 31);
-    if (EPI == E_FWD) {
-        __syncthreads();
-        bf16 *Cs = Ws;                             // BM x (BN + 8) bf16 staging
-        constexpr int LDC = BN + 8;
-        const float bv = (col < g.N && g.bias) ? g.bias[col] : 0.0f;
+        if (c == NCH - 1) {
+            // element q of acc: tile pixel wm*32 + 8(q/4) + 4(lane/32) + q%4, column col
+            const int tx0 = (t % ntx) * CV_TW;
+            const int rest = t / ntx;
+            const int ty0 = (rest % nty) * TH, b = rest / nty;
+            if (EPI == E_FWD) {
+                // Cs is rewritten only after the two barriers at the top of
+                // the loop, so the reads below are done by then
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-            float v = acc[q] + bv;
-            if (g.relu) v = fmaxf(v, 0.0f);
-            Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
-        }
-        __syncthreads();
-        for (int s = tid; s < BM * (BN / 8); s += 256) {
-            const int r = s / (BN / 8), cv = (s % (BN / 8)) * 8;
-            const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW, n = n0 + cv;
-            if (y >= g.gH || x >= g.gW || n >= g.N) continue;
-            const long long pix = ((long long)b * g.gH + y) * g.gW + x;
-            *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
-        }
-    } else {
-        if (col >= g.N) return;
+                for (int q = 0; q < 16; ++q) {
+                    const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    float v = acc[q] + bv;
+                    if (g.relu) v = fmaxf(v, 0.0f);
+                    Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
+                }
+                __syncthreads();
+                for (int sl = tid; sl < BM * (BN / 8); sl += 256) {
+                    const int r = sl / (BN / 8), cv = (sl % (BN / 8)) * 8;
+                    const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW, n = n0 + cv;
+                    if (y >= g.gH || x >= g.gW || n >= g.N) continue;
+                    const long long pix = ((long long)b * g.gH + y) * g.gW + x;
+                    *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) =
+                        *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
+                }
+            } else if (col < g.N) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-            const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW;
-            if (y >= g.gH || x >= g.gW) continue;
-            const long long m = ((long long)b * g.gH + y) * g.gW + x;
-            if (col < g.oc1) g.o1[m * g.oc1 + col] = acc[q];
-            else g.o2[m * (g.N - g.oc1) + (col - g.oc1)] = acc[q];
+                for (int q = 0; q < 16; ++q) {
+                    const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW;
+                    if (y >= g.gH || x >= g.gW) continue;
+                    const long long m = ((long long)b * g.gH + y) * g.gW + x;
+                    if (col < g.oc1) g.o1[m * g.oc1 + col] = acc[q];
+                    else g.o2[m * (g.N - g.oc1) + (col - g.oc1)] = acc[q];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
         }
+        if (!more) break;
+        t = tn;
+        c = cn;
     }
 }
-
-
 
 template <int AMODE, int BMODE, int EPI>
 hipError_t gemm(const GemmArgs &g, int nsplit, hipStream_t st)
@@ -699,17 +755,22 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
     }
 }
 
-// 3x3 convolutions with 32 output channels take the patch-staged kernel
-// (its weights for 32 channels fit beside the patch); wider outputs keep
-// the generic implicit GEMM, whose smaller LDS footprint keeps more blocks
-// resident (measured faster for 64 and 128 channels).
+// 3x3 convolutions with 32 output channels and up to 64 input channels take
+// the patch-staged kernel (its weights for 32 output channels fit beside
+// the patch); wider outputs keep the generic implicit GEMM, whose smaller
+// LDS footprint keeps more blocks resident (measured faster for 64 and 128
+// channels).  Tiles per block: up to 4, as long as the grid keeps about
+// 4096 blocks (16 per CU).
 template <int EPI>
 hipError_t conv3x3(const GemmArgs &g, hipStream_t st)
 {
-    if (g.N > 32) return gemm<A_CONV, B_W, EPI>(g, 1, st);
-    const int ntx = (g.gW + CV_TW - 1) / CV_TW;
-    const dim3 grd(g.gB * ((g.gH + 7) / 8) * ntx, 1);
-    hipLaunchKernelGGL((conv3x3_kernel<EPI, 128, 32>), grd, dim3(256), 0, st, g);
+    const int cin = g.ac1 + g.ac2;
+    if (g.N > 32 || (cin != 32 && cin != 64)) return gemm<A_CONV, B_W, EPI>(g, 1, st);
+    const int ntiles = g.gB * ((g.gH + 7) / 8) * ((g.gW + CV_TW - 1) / CV_TW);
+    const int tpb = std::max(1, std::min(4, ntiles / 4096));
+    const dim3 grd((ntiles + tpb - 1) / tpb, 1);
+    if (cin == 32) hipLaunchKernelGGL((conv3x3_kernel<EPI, 128, 32, 1>), grd, dim3(256), 0, st, g, tpb);
+    else hipLaunchKernelGGL((conv3x3_kernel<EPI, 128, 32, 2>), grd, dim3(256), 0, st, g, tpb);
     return hipGetLastError();
 }
 

@@ -357,18 +357,20 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_cache")
 
 
 @pytest.mark.timeout(600)
-def test_full_size_axial_iterations_against_oracle(L):
-    """The full 512x512x64 axial workload (984 views, 888 x 64 detector,
-    M = 12, continuation, x0 = 0) against the FP64 oracle's own run of it,
-    stored by tests/make_oracle_cache.py: D_L, and after every stored
-    iteration count K (1, 2, 20) the image on the sampled slices (ROI RMS
-    difference <= 0.5 HU), the FP64 cost of the whole volume (relative
-    1e-4) and the restart decisions of every step so far."""
-    path = os.path.join(CACHE, "cone_axial_512x64.npz")
+@pytest.mark.parametrize("name,iters", [("cone_axial_512x64", "1 2 20"), ("cone_helical_512x256", "1")])
+def test_full_size_iterations_against_oracle(L, name, iters):
+    """The full 3D workloads (512x512x64 axial: 984 views, 888 x 64
+    detector; 512x512x256 helical: 6888 views over 7 turns; M = 12,
+    continuation, x0 = 0) against the FP64 oracle's own run of them, stored
+    by tests/make_oracle_cache.py: D_L, and after every stored iteration
+    count K the image on the sampled slices (ROI RMS difference <= 0.5 HU),
+    the FP64 cost of the whole volume (relative 1e-4) and the restart
+    decisions of every step so far."""
+    path = os.path.join(CACHE, name + ".npz")
     if not os.path.exists(path):
-        pytest.skip("no stored oracle run: python tests/make_oracle_cache.py cone_axial_512x64 --iters 1 2 20")
+        pytest.skip("no stored oracle run: python tests/make_oracle_cache.py %s --iters %s" % (name, iters))
     c = np.load(path)
-    cfg = synth.get_config("cone_axial_512x64")
+    cfg = synth.get_config(name)
     M, beta, delta = int(c["M"]), float(c["beta"]), float(c["delta"])
     assert M == cfg["M"] and beta == cfg["beta"]
     ks = sorted(int(k[3:]) for k in c.files if k.startswith("x_k"))
@@ -378,7 +380,7 @@ def test_full_size_axial_iterations_against_oracle(L):
     data = _problem(cfg)
     plan, y, w, denom = _gpu_problem(L, cfg, M, data)
     e_dl = rel_l2(denom.reshape(shape)[sl].cpu().numpy(), c["DL"])
-    say("full-size axial: D_L rel %.2e on slices %s; stored K %s" % (e_dl, list(sl), ks))
+    say("full-size %s: D_L rel %.2e on slices %s; stored K %s" % (name, e_dl, list(sl), ks))
     assert e_dl <= 1e-5
     n = ks[-1] * M
     st = L.LalmState.zeros_like(torch.zeros(plan.image_elems, device=DEV))
