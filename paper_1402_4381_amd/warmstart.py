@@ -576,6 +576,8 @@ def main(argv=None):
     ap.add_argument("--volume", default=None,
                     help="3D workload: per-slice warm start with the committed weights (no training)")
     ap.add_argument("--out", default=None, help="JSON summary path")
+    ap.add_argument("--iters-target", type=int, default=None,
+                    help="iterations behind a training target (default: the warm-start settings' value)")
     ap.add_argument("--pairs-only", action="store_true",
                     help="only generate the training pairs and report their timing")
     ap.add_argument("--unet-timing", action="store_true",
@@ -598,6 +600,8 @@ def main(argv=None):
     if cfg["kind"] != 0:
         raise SystemExit("the warm start is 2D (one network per slice image)")
     ws = dict(synth.configs.UNET_WARMSTART)
+    if args.iters_target is not None:
+        ws["iters_target"] = args.iters_target
     pool = None
     if not args.eval_only and not args.unet_timing:
         # CPU workers are forked before the GPU is touched
