@@ -124,37 +124,41 @@ __device__ inline void init_rows(const GemmArgs &g, int m0, int tid, ARow *rs)
 
 // A tile (BM rows x BK) -> registers, one bf16x8 per slot.  A_CONV / A_UPG:
 // the K step's tap (or 2x2 phase) and channel range are uniform; a row's
-// gather is one bounds test and one address per vector.
+// gather is one bounds test and one address per vector.  Every slot issues
+// its load (an invalid one reads the start of its source), and the returned
+// mask (bit v: slot v is valid) zeroes the invalid ones when they are stored
+// to LDS: with neither a branch around a load nor a select on its value, a
+// wave waits for a load only where its data is stored, and the compiler can
+// count the loads in flight across loop iterations.
 template <int AMODE, int BM>
-__device__ inline void load_a(const GemmArgs &g, const ARow *rs, int m0, int k0, int tid, bf16x8 *ra)
+__device__ inline unsigned load_a(const GemmArgs &g, const ARow *rs, int m0, int k0, int tid, bf16x8 *ra)
 {
     constexpr int NVT = BM * BK / 8;                // vectors in the tile
     constexpr int NV = (NVT + 255) / 256;           // vectors per thread
+    unsigned mask = 0;
     if (AMODE == A_MC) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int s = tid + v * 256;
-            if (NVT % 256 != 0 && s >= NVT) {
-                ra[v] = zero8();
-                continue;
-            }
             // slot -> (pixel kk, channel vector) ; channels along M
             const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
             const int k = k0 + kk, m = m0 + mv;
-            bf16x8 r = zero8();
-            if (k < g.K && m < g.M) {
-                int b, y, x;
+            const bool ok = (NVT % 256 == 0 || s < NVT) && k < g.K && m < g.M;
+            long long off = 0;
+            if (ok) {
                 if (g.ab >= 0) {
+                    int b, y, x;
                     pix_decode(k, g.gH, g.gW, b, y, x);
                     const long long pix = ((long long)b * 2 * g.gH + 2 * y + (g.ab >> 1)) * (2 * g.gW) + 2 * x + (g.ab & 1);
-                    r = ld8(g.a1 + pix * g.ac1 + m);
+                    off = pix * g.ac1 + m;
                 } else {
-                    r = ld8(g.a1 + (long long)k * g.ac1 + m);
+                    off = (long long)k * g.ac1 + m;
                 }
             }
-            ra[v] = r;
+            ra[v] = ld8(g.a1 + off);
+            mask |= ok ? 1u << v : 0u;
         }
-        return;
+        return mask;
     }
     // uniform over the block: source, channel offset and pixel shift of this K step
     const bf16 *src;
@@ -189,13 +193,14 @@ __device__ inline void load_a(const GemmArgs &g, const ARow *rs, int m0, int k0,
             ok = ok && (unsigned)yy < (unsigned)g.gH && (unsigned)xx < (unsigned)g.gW;
         }
         const long long off = ok ? (long long)(r.pix + dpix) * cs + c0 + q : 0;
-        const bf16x8 val = ld8(src + off);
-        ra[v] = ok ? val : zero8();
+        ra[v] = ld8(src + off);
+        mask |= ok ? 1u << v : 0u;
     }
+    return mask;
 }
 
 template <int AMODE, int BM>
-__device__ inline void store_a(bf16 *As, int tid, const bf16x8 *ra)
+__device__ inline void store_a(bf16 *As, int tid, const bf16x8 *ra, unsigned mask)
 {
     constexpr int NVT = BM * BK / 8;
     constexpr int NV = (NVT + 255) / 256;
@@ -203,33 +208,39 @@ __device__ inline void store_a(bf16 *As, int tid, const bf16x8 *ra)
     for (int v = 0; v < NV; ++v) {
         const int s = tid + v * 256;
         if (NVT % 256 != 0 && s >= NVT) continue;
+        const bf16x8 val = (mask >> v) & 1u ? ra[v] : zero8();
         if (AMODE == A_MC) {
             const int kk = s / (BM / 8), mv = (s % (BM / 8)) * 8;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) As[(mv + i) * LDK + kk] = ra[v][i];
+            for (int i = 0; i < 8; ++i) As[(mv + i) * LDK + kk] = val[i];
         } else {
             const int mm = s / (BK / 8), q = (s % (BK / 8)) * 8;
-            *reinterpret_cast<bf16x8 *>(As + mm * LDK + q) = ra[v];
+            *reinterpret_cast<bf16x8 *>(As + mm * LDK + q) = val;
         }
     }
 }
 
-// B tile (BN x BK) -> registers; BN * BK / 8 vectors spread over the threads
+// B tile (BN x BK) -> registers; BN * BK / 8 vectors spread over the
+// threads.  B_W: every slot loads (an invalid one reads row 0) and the mask
+// zeroes it at the store, as for A; B_NC: gathers under the lane mask.
 template <int BMODE, int BN>
-__device__ inline void load_b(const GemmArgs &g, int n0, int k0, int tid, bf16x8 *rb)
+__device__ inline unsigned load_b(const GemmArgs &g, int n0, int k0, int tid, bf16x8 *rb)
 {
     constexpr int NVT = BN * BK / 8;                // total vectors
     constexpr int NV = (NVT + 255) / 256;
+    unsigned mask = 0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int s = tid + v * 256;
-        bf16x8 r = zero8();
-        if (s < NVT) {
-            if (BMODE == B_W) {
-                const int nn = s / (BK / 8), q = (s % (BK / 8)) * 8;
-                const int n = n0 + nn;
-                if (n < g.N) r = ld8(g.w + (long long)n * g.K + k0 + q);
-            } else {
+        if (BMODE == B_W) {
+            const int nn = s / (BK / 8), q = (s % (BK / 8)) * 8;
+            const int n = n0 + nn;
+            const bool ok = (NVT % 256 == 0 || s < NVT) && n < g.N;
+            rb[v] = ld8(g.w + (ok ? (long long)n * g.K + k0 + q : 0));
+            mask |= ok ? 1u << v : 0u;
+        } else {
+            bf16x8 r = zero8();
+            if (s < NVT) {
                 const int kk = s / (BN / 8), nv = (s % (BN / 8)) * 8;
                 const int k = k0 + kk, n = n0 + nv;
                 if (k < g.K && n < g.N) {
@@ -244,13 +255,15 @@ __device__ inline void load_b(const GemmArgs &g, int n0, int k0, int tid, bf16x8
                     r = gather_ch(g.b1, g.b2, g.bc1, g.bc2, g.gH, g.gW, b, y, x, c);
                 }
             }
+            rb[v] = r;
+            mask |= 1u << v;
         }
-        rb[v] = r;
     }
+    return mask;
 }
 
 template <int BMODE, int BN>
-__device__ inline void store_b(bf16 *Bs, int tid, const bf16x8 *rb)
+__device__ inline void store_b(bf16 *Bs, int tid, const bf16x8 *rb, unsigned mask)
 {
     constexpr int NVT = BN * BK / 8;
     constexpr int NV = (NVT + 255) / 256;
@@ -258,13 +271,14 @@ __device__ inline void store_b(bf16 *Bs, int tid, const bf16x8 *rb)
     for (int v = 0; v < NV; ++v) {
         const int s = tid + v * 256;
         if (s >= NVT) continue;
+        const bf16x8 val = (mask >> v) & 1u ? rb[v] : zero8();
         if (BMODE == B_W) {
             const int nn = s / (BK / 8), q = (s % (BK / 8)) * 8;
-            *reinterpret_cast<bf16x8 *>(Bs + nn * LDK + q) = rb[v];
+            *reinterpret_cast<bf16x8 *>(Bs + nn * LDK + q) = val;
         } else {
             const int kk = s / (BN / 8), nv = (s % (BN / 8)) * 8;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) Bs[(nv + i) * LDK + kk] = rb[v][i];
+            for (int i = 0; i < 8; ++i) Bs[(nv + i) * LDK + kk] = val[i];
         }
     }
 }
@@ -300,20 +314,30 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
+    // two register stages take turns: the tile of step k + 2 is loaded while
+    // step k computes, so two K tiles are in flight per block.  Steps run in
+    // pairs; past the last K tile a step loads the last tile again, and a
+    // step past kend (an odd step count) stores zeros, so the loop has no
+    // branch around a load and one exit.
+    bf16x8 ra2[NVA], rb2[NVB];
+    unsigned ma = 0, mb = 0, ma2 = 0, mb2 = 0;
+    const int klast = kbeg < kend ? kbeg + (kend - kbeg - 1) / BK * BK : kbeg;
     int buf = 0;
     if (kbeg < kend) {
-        load_a<AMODE, BM>(g, rs, m0, kbeg, tid, ra);
-        load_b<BMODE, BN>(g, n0, kbeg, tid, rb);
+        ma = load_a<AMODE, BM>(g, rs, m0, kbeg, tid, ra);
+        mb = load_b<BMODE, BN>(g, n0, kbeg, tid, rb);
+        ma2 = load_a<AMODE, BM>(g, rs, m0, min(kbeg + BK, klast), tid, ra2);
+        mb2 = load_b<BMODE, BN>(g, n0, min(kbeg + BK, klast), tid, rb2);
     }
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    auto step = [&](int k0, bf16x8 *xa, bf16x8 *xb, unsigned &mxa, unsigned &mxb) {
+        const unsigned live = k0 < kend ? ~0u : 0u;
         bf16 *as_buf = smem + buf * (BM * LDK), *bs_buf = smem + 2 * BM * LDK + buf * (BN * LDK);
-        store_a<AMODE, BM>(as_buf, tid, ra);
-        store_b<BMODE, BN>(bs_buf, tid, rb);
+        store_a<AMODE, BM>(as_buf, tid, xa, mxa & live);
+        store_b<BMODE, BN>(bs_buf, tid, xb, mxb & live);
         __syncthreads();
-        if (k0 + BK < kend) {                      // prefetch the next tile
-            load_a<AMODE, BM>(g, rs, m0, k0 + BK, tid, ra);
-            load_b<BMODE, BN>(g, n0, k0 + BK, tid, rb);
-        }
+        const int kn = min(k0 + 2 * BK, klast);    // prefetch two tiles ahead
+        mxa = load_a<AMODE, BM>(g, rs, m0, kn, tid, xa);
+        mxb = load_b<BMODE, BN>(g, n0, kn, tid, xb);
         const bf16 *as = as_buf + (wm * 32 * WMT + (lane & 31)) * LDK + 8 * (lane >> 5);
         const bf16 *bs = bs_buf + (wn * 32 * WNT + (lane & 31)) * LDK + 8 * (lane >> 5);
 #pragma unroll
@@ -330,6 +354,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         buf ^= 1;
+    };
+    for (int k0 = kbeg; k0 < kend; k0 += 2 * BK) {
+        step(k0, ra, rb, ma, mb);
+        step(k0 + BK, ra2, rb2, ma2, mb2);
     }
 
     // element t of acc[i][j]: row wm*32*WMT + 32 i + 8(t/4) + 4(lane/32) + t%4,
@@ -398,14 +426,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 // 3x3 convolution (forward, or the input gradient with mirrored taps) as an
 // implicit GEMM whose input tile is staged once per chunk of 32 channels.
 // A block owns BN output channels and a run of consecutive TH x 16 pixel
-// tiles.  The BN x 9 x cin weights (cin = 32 NCH) go to LDS once; then for
-// each (tile, chunk of 32 input channels) it stores the (TH + 2) x 18 pixel
-// patch (zero outside the image), already in registers, to LDS, issues the
-// loads of the next patch, and every wave runs 9 taps x 2 MFMA k-steps
-// reading its operands from LDS, so the nine taps re-read the patch in LDS
-// instead of memory and the next patch is in flight meanwhile.  Same MFMA,
-// operand layouts and epilogues as gemm_kernel (E_FWD: bias, ReLU, bf16
-// NHWC; E_DG: FP32 split output).
+// tiles.  The BN x 9 x cin weights (cin = 32 NCH) go to LDS once; the work
+// is a sequence of items (tile, chunk of 32 input channels).  For each item
+// the block stores the (TH + 2) x 18 pixel patch (zero outside the image),
+// already in registers, to LDS and issues the loads of the item two places
+// further on (two register sets take turns), so two patches are in flight
+// while every wave runs 9 taps x 2 MFMA k-steps reading its operands from
+// LDS: the nine taps re-read the patch in LDS instead of memory.  Same MFMA,
+// operand layouts, summation order (chunk, tap, k-step) and epilogues as
+// gemm_kernel (E_FWD: bias, ReLU, bf16 NHWC; E_DG: FP32 split output).
 constexpr int CV_TW = 16;              // tile width (pixels)
 constexpr int CV_LDP = 40;             // LDS stride per patch pixel / weight tap (bf16): 32 + 8
 constexpr int CV_LDW = 9 * CV_LDP;     // LDS stride per weight row (9 taps)
@@ -428,14 +457,15 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_
     const int wm = wv % (BM / 32), wn = wv / (BM / 32);
     const int ntx = (g.gW + CV_TW - 1) / CV_TW, nty = (g.gH + TH - 1) / TH;
     const int ntiles = g.gB * nty * ntx;
-    int t = blockIdx.x * tiles_per_block;
-    const int tend = min(ntiles, t + tiles_per_block);
-    if (t >= tend) return;
+    const int t0 = blockIdx.x * tiles_per_block;
+    const int nitem = (min(ntiles, t0 + tiles_per_block) - t0) * NCH;   // items (tile, chunk)
+    if (nitem <= 0) return;
     const int n0 = blockIdx.y * BN;
     const int cin = g.ac1 + g.ac2;                 // 32 NCH
 
-    // the patch of (tile tt, chunk cc) -> registers, one vector per slot
-    auto load_patch = [&](int tt, int cc, bf16x8 *rp) {
+    // the patch of item it -> registers, one vector per slot
+    auto load_patch = [&](int it, bf16x8 *rp) {
+        const int tt = t0 + it / NCH, cc = it % NCH;
         const int tx0 = (tt % ntx) * CV_TW;
         const int rest = tt / ntx;
         const int ty0 = (rest % nty) * TH, b = rest / nty;
@@ -454,8 +484,9 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_
         }
     };
 
-    bf16x8 rp[NP];
-    load_patch(t, 0, rp);
+    bf16x8 ra[NP], rb[NP];
+    load_patch(0, ra);
+    if (nitem > 1) load_patch(1, rb);
     {
         // all weights, [chunk][N][tap][32 channels], rows from K = tap * cin + c
         bf16x8 rw[NW];
@@ -487,8 +518,10 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_
     floatx16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    int c = 0;
-    for (;;) {
+
+    // one item: its patch rp -> LDS, loads of item it + 2 into rp, the MFMAs,
+    // and after the tile's last chunk the epilogue
+    auto item = [&](int it, bf16x8 *rp) {
         __syncthreads();                           // the previous item's readers are done
 #pragma unroll
         for (int v = 0; v < NP; ++v) {
@@ -497,13 +530,8 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_
             *reinterpret_cast<bf16x8 *>(Ps + (sl >> 2) * CV_LDP + 8 * (sl & 3)) = rp[v];
         }
         __syncthreads();
-        int tn = t, cn = c + 1;
-        if (cn == NCH) {
-            cn = 0;
-            ++tn;
-        }
-        const bool more = tn < tend;
-        if (more) load_patch(tn, cn, rp);          // in flight during the MFMAs
+        if (it + 2 < nitem) load_patch(it + 2, rp);  // in flight during two items
+        const int c = it % NCH;
         const bf16 *ws = Ws + (c * BN + wn * 32 + (lane & 31)) * CV_LDW + 8 * (lane >> 5);
 #pragma unroll
         for (int tp = 0; tp < 9; ++tp) {
@@ -516,47 +544,50 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc, 0, 0, 0);
             }
         }
-        if (c == NCH - 1) {
-            // element q of acc: tile pixel wm*32 + 8(q/4) + 4(lane/32) + q%4, column col
-            const int tx0 = (t % ntx) * CV_TW;
-            const int rest = t / ntx;
-            const int ty0 = (rest % nty) * TH, b = rest / nty;
-            if (EPI == E_FWD) {
-                // Cs is rewritten only after the two barriers at the top of
-                // the loop, so the reads below are done by then
+        if (c != NCH - 1) return;
+        // element q of acc: tile pixel wm*32 + 8(q/4) + 4(lane/32) + q%4, column col
+        const int tt = t0 + it / NCH;
+        const int tx0 = (tt % ntx) * CV_TW;
+        const int rest = tt / ntx;
+        const int ty0 = (rest % nty) * TH, b = rest / nty;
+        if (EPI == E_FWD) {
+            // Cs is rewritten only after the two barriers at the top of the
+            // next item, so the reads below are done by then
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    float v = acc[q] + bv;
-                    if (g.relu) v = fmaxf(v, 0.0f);
-                    Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
-                }
-                __syncthreads();
-                for (int sl = tid; sl < BM * (BN / 8); sl += 256) {
-                    const int r = sl / (BN / 8), cv = (sl % (BN / 8)) * 8;
-                    const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW, n = n0 + cv;
-                    if (y >= g.gH || x >= g.gW || n >= g.N) continue;
-                    const long long pix = ((long long)b * g.gH + y) * g.gW + x;
-                    *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) =
-                        *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
-                }
-            } else if (col < g.N) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW;
-                    if (y >= g.gH || x >= g.gW) continue;
-                    const long long m = ((long long)b * g.gH + y) * g.gW + x;
-                    if (col < g.oc1) g.o1[m * g.oc1 + col] = acc[q];
-                    else g.o2[m * (g.N - g.oc1) + (col - g.oc1)] = acc[q];
-                }
+            for (int q = 0; q < 16; ++q) {
+                const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                float v = acc[q] + bv;
+                if (g.relu) v = fmaxf(v, 0.0f);
+                Cs[r * LDC + wn * 32 + (lane & 31)] = (bf16)v;
             }
+            __syncthreads();
+            for (int sl = tid; sl < BM * (BN / 8); sl += 256) {
+                const int r = sl / (BN / 8), cv = (sl % (BN / 8)) * 8;
+                const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW, n = n0 + cv;
+                if (y >= g.gH || x >= g.gW || n >= g.N) continue;
+                const long long pix = ((long long)b * g.gH + y) * g.gW + x;
+                *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
+            }
+        } else if (col < g.N) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+            for (int q = 0; q < 16; ++q) {
+                const int r = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const int y = ty0 + r / CV_TW, x = tx0 + r % CV_TW;
+                if (y >= g.gH || x >= g.gW) continue;
+                const long long m = ((long long)b * g.gH + y) * g.gW + x;
+                if (col < g.oc1) g.o1[m * g.oc1 + col] = acc[q];
+                else g.o2[m * (g.N - g.oc1) + (col - g.oc1)] = acc[q];
+            }
         }
-        if (!more) break;
-        t = tn;
-        c = cn;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    };
+
+    for (int it = 0;; it += 2) {
+        item(it, ra);
+        if (it + 1 >= nitem) break;
+        item(it + 1, rb);
+        if (it + 2 >= nitem) break;
     }
 }
 
@@ -615,6 +646,7 @@ template <int BM, int BN>
 __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
 {
     static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32x32");
+    static_assert((LDK / 2) % 8 == 4 && BK == 32, "the bank rotation of store2 assumes 20-word rows and 16 pixel pairs");
     constexpr int PA = BM * BK / 16;                 // A pixel pairs x channel vectors in the tile
     constexpr int PB = BN * BK / 16;
     constexpr int NA = (PA + 255) / 256, NB = (PB + 255) / 256;
@@ -626,7 +658,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
     const int kbeg = blockIdx.z * g.klen, kend = min(g.K, kbeg + g.klen);
     const int H = g.gH, W = g.gW;
 
-    // A slots: pixel pair kp (pixels 2kp, 2kp+1 of the tile), channels mv..mv+7
+    // A slots: pixel pair kp (pixels 2kp, 2kp+1 of the tile), channels
+    // mv..mv+7; the pair index runs fastest over the lanes (see store2)
     PixState pa[NA][2];
     int am[NA];
     bool aon[NA];
@@ -634,8 +667,8 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
     for (int v = 0; v < NA; ++v) {
         const int s = tid + 256 * v;
         aon[v] = PA % 256 == 0 || s < PA;
-        const int kp = s / (BM / 8);
-        am[v] = m0 + (s % (BM / 8)) * 8;
+        const int kp = s % (BK / 2);
+        am[v] = m0 + (s / (BK / 2)) * 8;
         pa[v][0] = pix_init(kbeg + 2 * kp, H, W);
         pa[v][1] = pix_init(kbeg + 2 * kp + 1, H, W);
     }
@@ -647,7 +680,7 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
 #pragma unroll
     for (int v = 0; v < NB; ++v) {
         const int s = tid + 256 * v;
-        const int kp = s / (BN / 8), n = n0 + (s % (BN / 8)) * 8;
+        const int kp = s % (BK / 2), n = n0 + (s / (BK / 2)) * 8;
         bon[v] = (PB % 256 == 0 || s < PB) && n < g.N;
         const int cin = g.bc1 + g.bc2;
         const int tap = bon[v] ? n / cin : 0, c = bon[v] ? n - tap * cin : 0;
@@ -701,17 +734,24 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
             pix_advance(pb[v][1], BK, H, W);
         }
     };
-    // transposed stores: element i of the two pixels' vectors -> one 32-bit word
-    auto store2 = [&](bf16 *S, int per_row, int n_pairs, int s, const bf16x8 &v0, const bf16x8 &v1) {
+    // transposed stores: element e of the two pixels' vectors -> one 32-bit
+    // word of row mv + e.  The 16 lanes of a channel group write 16
+    // consecutive words of one row; the next group's rows are 8 further on,
+    // 160 words, the same banks, so odd groups write their elements rotated
+    // by 4 (rows 4 or 12 apart, 16 banks further): a 32-lane half-wave
+    // covers the 32 banks once.
+    auto store2 = [&](bf16 *S, int n_pairs, int s, const bf16x8 &v0, const bf16x8 &v1) {
         if (s >= n_pairs) return;
-        const int kp = s / (per_row / 8), mv = (s % (per_row / 8)) * 8;
+        const int kp = s % (BK / 2), grp = s / (BK / 2), mv = grp * 8;
+        const bool odd = grp & 1;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+            const int e = odd ? (i + 4) & 7 : i;
             bf16x2 pr;
-            pr[0] = v0[i];
-            pr[1] = v1[i];
-            *reinterpret_cast<bf16x2 *>(S + (mv + i) * LDK + 2 * kp) = pr;
+            pr[0] = odd ? v0[(i + 4) & 7] : v0[i];
+            pr[1] = odd ? v1[(i + 4) & 7] : v1[i];
+            *reinterpret_cast<bf16x2 *>(S + (mv + e) * LDK + 2 * kp) = pr;
         }
     };
 
@@ -726,9 +766,9 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
     }
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-        for (int v = 0; v < NA; ++v) store2(As[buf], BM, PA, tid + 256 * v, ra[v][0], ra[v][1]);
+        for (int v = 0; v < NA; ++v) store2(As[buf], PA, tid + 256 * v, ra[v][0], ra[v][1]);
 #pragma unroll
-        for (int v = 0; v < NB; ++v) store2(Bs[buf], BN, PB, tid + 256 * v, rb[v][0], rb[v][1]);
+        for (int v = 0; v < NB; ++v) store2(Bs[buf], PB, tid + 256 * v, rb[v][0], rb[v][1]);
         __syncthreads();
         if (k0 + BK < kend) {                      // prefetch the next tile
             advance();
