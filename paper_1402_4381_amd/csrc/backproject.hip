@@ -74,12 +74,16 @@ __device__ inline double block_sum_256(double v, double *lds)
 // reweighted least squares on Chebyshev nodes (max error 1.7e-6 rad), and
 // atan(t) = pi/2 - atan(1/t) above 1.  Used only to bound channel windows;
 // the window margin covers its error.  (The 3D kernel and the 2D line
-// kernel both use it.)
+// kernel both use it.)  The window set-up also takes the hardware
+// reciprocal and square root (v_rcp_f32, v_sqrt_f32, about 1 ulp) where a
+// correctly rounded division or root would cost a dozen instructions: their
+// results only place windows that carry a margin of at least 0.01 channel or
+// row, far above those errors.
 __device__ inline float atan_window(float t)
 {
     const float at = fabsf(t);
     const bool big = at > 1.0f;
-    const float z = big ? __frcp_rn(at) : at;
+    const float z = big ? __builtin_amdgcn_rcpf(at) : at;   // hardware reciprocal, 1 ulp
     const float z2 = z * z;
     float p = fmaf(z2, -0.011719409376382828f, 0.05264794081449509f);
     p = fmaf(z2, p, -0.11642685532569885f);
@@ -166,17 +170,17 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
         for (int kv = kv_lo; kv < kv_hi; ++kv) {
             const ViewRec V = A.views[kv];
             {
-                const float tmax = sqrtf((bxc - V.sx) * (bxc - V.sx) + (byc - V.sy) * (byc - V.sy)) + bhd;
+                const float tmax = __builtin_amdgcn_sqrtf((bxc - V.sx) * (bxc - V.sx) + (byc - V.sy) * (byc - V.sy)) + bhd;
                 const float reach = fmaf(K.zreach, tmax, 1.01f);
                 if ((float)kb > V.z0 + reach || (float)(kb + KZ - 1) < V.z0 - reach) continue;
             }
             const float ddx = X - V.sx, ddy = Y - V.sy;
             const float dc = -(ddx * V.cb + ddy * V.sb);
             const float dp = ddx * V.sb - ddy * V.cb;
-            const float gam = atan_window(__fdividef(dp, dc));   // dc > 0: in front of the source
+            const float gam = atan_window(dp * __builtin_amdgcn_rcpf(dc));   // dc > 0: in front of the source
             const float bc = fmaf(gam, K.dsd_over_ds, K.bin_center);
-            const float dist = sqrtf(fmaf(ddx, ddx, ddy * ddy));
-            const float hw = dist > 2.0f * K.dmax ? K.dmax / (dist - K.dmax) * K.dsd_over_ds + 0.05f
+            const float dist = __builtin_amdgcn_sqrtf(fmaf(ddx, ddx, ddy * ddy));
+            const float hw = dist > 2.0f * K.dmax ? K.dmax * __builtin_amdgcn_rcpf(dist - K.dmax) * K.dsd_over_ds + 0.05f
                                                   : (float)K.nb;
             const int b0 = max(0, (int)ceilf(bc - hw));
             const int b1 = min(K.nb - 1, (int)floorf(bc + hw));
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                     const float qz = fmaf(fs, rz.k, rz.m);
                     // detector rows per slice (it only places the row windows,
                     // which carry a 0.01-row margin)
-                    const float inv = __fdividef(K.inv_dt, qz);
+                    const float inv = K.inv_dt * __builtin_amdgcn_rcpf(qz);
                     // row of slice coordinate k -+ 1: (k -+ 1 - z0) inv + rc
                     //   = -zk inv + (rc -+ inv), with zk = z0 - k
                     const float c_lo = rc_lo - inv, c_hi = rc_hi + inv;
@@ -319,7 +323,7 @@ __device__ inline float bin_coord(const GeoK &K, const ViewRec &V, float px, flo
     const float ddx = px - V.sx, ddy = py - V.sy;
     const float dc = -(ddx * V.cb + ddy * V.sb);
     const float dp = ddx * V.sb - ddy * V.cb;
-    return fmaf(atan_window(__fdividef(dp, dc)), K.dsd_over_ds, K.bin_center);
+    return fmaf(atan_window(dp * __builtin_amdgcn_rcpf(dc)), K.dsd_over_ds, K.bin_center);
 }
 
 __device__ inline void wave_lds_sync()
