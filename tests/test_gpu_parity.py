@@ -377,7 +377,10 @@ def test_full_size_iterations_against_oracle(L, name, iters):
     assert ks, "the stored run holds no image yet"
     sl = c["slices"]
     shape = ora.image_shape(cfg)
-    data = _problem(cfg)
+    say("full-size %s: synthetic data (host workers)" % name)
+    # the default host worker pool: one worker takes many minutes on the helical scan
+    data = synth.make_problem_data(cfg)
+    say("full-size %s: data ready, planning and D_L" % name)
     plan, y, w, denom = _gpu_problem(L, cfg, M, data)
     e_dl = rel_l2(denom.reshape(shape)[sl].cpu().numpy(), c["DL"])
     say("full-size %s: D_L rel %.2e on slices %s; stored K %s" % (name, e_dl, list(sl), ks))
