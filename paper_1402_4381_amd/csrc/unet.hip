@@ -1065,20 +1065,30 @@ __global__ void __launch_bounds__(256) sum_chunk_kernel(const float *v, long lon
 
 // out[i] = sum_s part[s][i] in a fixed order: 32 outputs x 8 split lanes per
 // block (lane j sums splits j, j+8, ...), lanes combined in order
-__global__ void __launch_bounds__(256) reduce_parts_kernel(const float *part, int ns, long long n, float *out)
+// out[i] = sum over the ns splits of part[k][i], in a fixed order: a block
+// of 1024 threads takes 32 outputs; thread (k-lane sy, output ox) sums
+// splits sy, sy + 32, ... into eight running sums (eight loads in flight),
+// adds them pairwise, and the first wave adds the 32 k-lanes in order.
+__global__ void __launch_bounds__(1024) reduce_parts_kernel(const float *part, int ns, long long n, float *out)
 {
-    __shared__ float red[8][33];
+    __shared__ float red[32][33];
     const int ox = threadIdx.x & 31, sy = threadIdx.x >> 5;
     const long long i = (long long)blockIdx.x * 32 + ox;
-    float s = 0.0f;
-    if (i < n)
-        for (int k = sy; k < ns; k += 8) s += part[(long long)k * n + i];
-    red[sy][ox] = s;
+    float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (i < n) {
+        int k = sy;
+        for (; k + 7 * 32 < ns; k += 8 * 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] += part[(long long)(k + 32 * u) * n + i];
+        }
+        for (; k < ns; k += 32) s[0] += part[(long long)k * n + i];
+    }
+    red[sy][ox] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     if (sy == 0 && i < n) {
         float t = red[0][ox];
 #pragma unroll
-        for (int j = 1; j < 8; ++j) t += red[j][ox];
+        for (int j = 1; j < 32; ++j) t += red[j][ox];
         out[i] = t;
     }
 }
@@ -1307,7 +1317,7 @@ hipError_t wgrad_gemm(lalm_unet *n, GemmArgs &g, float *dst, hipStream_t st)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long cnt = (long long)g.M * g.N;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt, 32)), dim3(256), 0, st, n->part, (int)ns, cnt, dst);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(cnt, 32)), dim3(1024), 0, st, n->part, (int)ns, cnt, dst);
     return hipGetLastError();
 }
 
@@ -1360,7 +1370,7 @@ hipError_t bias_grad(lalm_unet *n, const bf16 *dz, int C, long long P, float *ds
     const int ns = (int)((P + chunk - 1) / chunk);
     hipError_t e = colsum(dz, nullptr, C, P, chunk, n->part, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(C, 32)), dim3(256), 0, st, n->part, ns, (long long)C, dst);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(C, 32)), dim3(1024), 0, st, n->part, ns, (long long)C, dst);
     return hipGetLastError();
 }
 
@@ -1576,9 +1586,9 @@ lalm_status loss_grad_impl(lalm_unet *n, const float *params, const float *x, co
     {
         const int chunk = 4096, ns = (int)((P + chunk - 1) / chunk);
         UCHK("head wgrad", colsum(n->d1b, n->dout, 32, P, chunk, n->part, st));
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, n->part, ns, 32LL, grad + n->woff[HEAD]);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, n->part, ns, 32LL, grad + n->woff[HEAD]);
         hipLaunchKernelGGL(sum_chunk_kernel, dim3(ns), dim3(256), 0, st, n->dout, P, chunk, n->part);
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, n->part, ns, 1LL, grad + n->boff[HEAD]);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(1024), 0, st, n->part, ns, 1LL, grad + n->boff[HEAD]);
         hipLaunchKernelGGL(head_bwd_kernel, dim3(nblk(P * 32)), dim3(256), 0, st, n->dout, n->d1b,
                            params + n->woff[HEAD], n->dzA, P);
         UCHK("unet head backward", hipGetLastError());
@@ -1665,7 +1675,7 @@ lalm_status loss_grad_impl(lalm_unet *n, const float *params, const float *x, co
         hipLaunchKernelGGL(conv1_wgrad_kernel, dim3(ns), dim3(256), 0, st, x, (float)in_scale, dz, n->part, B, H, W,
                            chunk);
         // part[s][c*10 + t] -> weights [c][t] (t < 9) and bias [c]
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(320, 32)), dim3(256), 0, st, n->part, ns, 320LL, n->gB);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(320, 32)), dim3(1024), 0, st, n->part, ns, 320LL, n->gB);
         hipLaunchKernelGGL(scatter_conv1_kernel, dim3(1), dim3(320), 0, st, n->gB, grad + n->woff[E1A],
                            grad + n->boff[E1A]);
         UCHK("e1a wgrad", hipGetLastError());
