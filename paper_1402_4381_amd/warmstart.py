@@ -557,6 +557,195 @@ def run_volume(name, weights, iters_in=2, iters_ref=150, inner_ref=10, max_iters
     return res
 
 
+def _volume_inputs(lalm, torch, synth, cfg, plan, seed, dev):
+    """Subset-major device sinogram y, weights w and D_L of one synthetic
+    scan of a 3D workload (seed None: the workload's own scan), and the
+    host data (for plans with another subset count)."""
+    data = synth.make_problem_data(cfg, seed)
+    vos = torch.as_tensor(plan.view_of_slot, dtype=torch.long, device=dev)
+    y = torch.as_tensor(data["y"].astype(np.float32), device=dev).index_select(0, vos).reshape(-1).contiguous()
+    w = torch.as_tensor(data["w"].astype(np.float32), device=dev).index_select(0, vos).reshape(-1).contiguous()
+    denom = torch.empty(plan.image_elems, device=dev)
+    lalm.lalm_sqs_denom(plan, w, denom)
+    return data, y, w, denom
+
+
+def train_volume(name, seeds, weights_out, iters_in=2, iters_target=30, n_inner=16, epochs=10, batch=8, lr=1e-3,
+                 dev="cuda:0"):
+    """Train the warm-start network on the axial slices of 3D scans.
+
+    For every seed a synthetic scan of the workload (its geometry, noise and
+    beta, another phantom) is reconstructed by OS-LALM with continuation and
+    n_inner inner FISTA iterations; the pairs are the slices after iters_in
+    iterations and after iters_target iterations (with n_inner = 16 the
+    latter lie within about 1 HU of x*).  The network, loss and optimizer
+    are the 2D pipeline's (512^2 slices, ROI mask, HU loss, Adam)."""
+    import torch
+    import synth
+    from paper_1402_4381_amd import lalm
+    cfg = synth.get_config(name)
+    if cfg["kind"] == 0:
+        raise SystemExit("train_volume is for the 3D workloads")
+    M = cfg["M"]
+    nz, ny, nx = cfg["nz"], cfg["ny"], cfg["nx"]
+    plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    X = torch.empty(len(seeds) * nz, ny * nx, device=dev)
+    T = torch.empty(len(seeds) * nz, ny * nx, device=dev)
+    t0 = time.perf_counter()
+    gpu_s = 0.0
+    for i, seed in enumerate(seeds):
+        _, y, w, denom = _volume_inputs(lalm, torch, synth, cfg, plan, seed, dev)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        st = lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+        lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, iters_in * M, n_inner=n_inner)
+        X[i * nz:(i + 1) * nz].copy_(st.x.view(nz, ny * nx))
+        lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, (iters_target - iters_in) * M, n_inner=n_inner)
+        T[i * nz:(i + 1) * nz].copy_(st.x.view(nz, ny * nx))
+        torch.cuda.synchronize()
+        gpu_s += time.perf_counter() - g0
+        print("volume pairs %d/%d (seed %d): %.1f s (GPU %.1f s)" % (i + 1, len(seeds), seed,
+                                                                    time.perf_counter() - t0, gpu_s), flush=True)
+        del y, w, denom, st
+    torch.cuda.empty_cache()
+    # 512^2 slices on the same in-plane grid and field of view as the 2D workload
+    pipe = Pipeline(synth.get_config("fan2d_512"), dev=dev)
+    params, tinfo = pipe.train(X, T, epochs, batch, lr)
+    os.makedirs(os.path.dirname(os.path.abspath(weights_out)), exist_ok=True)
+    np.save(weights_out, params.cpu().numpy())
+    print("weights written to", weights_out, flush=True)
+    return dict(workload=name, seeds=[int(v) for v in seeds], slices=int(X.shape[0]), iters_in=iters_in,
+                iters_target=iters_target, n_inner=n_inner, pairs_wall_s=round(time.perf_counter() - t0, 1),
+                pairs_gpu_s=round(gpu_s, 1), train=tinfo)
+
+
+def eval_volume(name, weights, n_inner=16, iters_in=2, max_iters=60, warm_iters=20, polish_tol_hu=0.005,
+                polish_budget_s=240.0, batch=8, dev="cuda:0"):
+    """Run to 1 HU on the workload's own 3D scan (held out from training),
+    plain against warm-started, both with n_inner inner FISTA iterations.
+
+    x* is built as the benchmark builds it (Sec. V measures against a
+    converged one-subset reference): OS-LALM-M-c-n for warm_iters
+    iterations, then the one-subset method from that image until its change
+    over 10 iterations is below polish_tol_hu (or the time budget).  The warm
+    start: iters_in iterations, the network on every axial slice, the FP64
+    cost guard of the whole volume, the state reset, then iterations."""
+    import torch
+    import synth
+    from paper_1402_4381_amd import lalm
+    cfg = synth.get_config(name)
+    M = cfg["M"]
+    nz, ny, nx = cfg["nz"], cfg["ny"], cfg["nx"]
+    plan = lalm.lalm_plan_geometry(synth.geometry_of(cfg), M)
+    beta, delta = cfg["beta"], synth.configs.delta_mu(cfg)
+    radius, hu, in_scale = synth.roi_radius(cfg), synth.HU_PER_MU, 1.0 / synth.MU_WATER
+    t0 = time.perf_counter()
+    data, y, w, denom = _volume_inputs(lalm, torch, synth, cfg, plan, None, dev)
+    print("eval volume %s: inputs in %.1f s" % (name, time.perf_counter() - t0), flush=True)
+    r64 = torch.zeros(1, dtype=torch.float64, device=dev)
+    c64 = torch.zeros(3, dtype=torch.float64, device=dev)
+
+    def rmsd(a, b):
+        lalm.lalm_roi_rmsd_f64(plan, a, b, radius, r64)
+        return float(r64.item()) * hu
+
+    def cost(x):
+        lalm.lalm_cost_f64(plan, y, w, beta, delta, x, c64)
+        return float(c64[0].item())
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        f()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    zero = lambda: lalm.LalmState.zeros_like(torch.zeros(plan.image_elems, device=dev))
+    # x*
+    st = zero()
+    timed(lambda: lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, warm_iters * M, n_inner=n_inner))
+    p1 = lalm.lalm_plan_geometry(synth.geometry_of(cfg), 1)
+    vos = torch.as_tensor(p1.view_of_slot, dtype=torch.long, device=dev)
+    y1 = torch.as_tensor(data["y"].astype(np.float32), device=dev).index_select(0, vos).reshape(-1).contiguous()
+    w1 = torch.as_tensor(data["w"].astype(np.float32), device=dev).index_select(0, vos).reshape(-1).contiguous()
+    del data
+    xs = zero()
+    xs.x.copy_(st.x)
+    del st
+    prev = xs.x.clone()
+    k, t_pol, change = 0, 0.0, None
+    while t_pol < polish_budget_s:
+        t_pol += timed(lambda: lalm.lalm_iterate(p1, y1, w1, denom, beta, delta, xs, 10, n_inner=n_inner))
+        k += 10
+        change = rmsd(xs.x, prev)
+        prev.copy_(xs.x)
+        print("  x* one-subset iteration %d: change over 10 iterations %.4f HU (%.1f s)" % (k, change, t_pol),
+              flush=True)
+        if change < polish_tol_hu:
+            break
+    x_star = xs.x
+    del y1, w1, p1, prev
+    torch.cuda.empty_cache()
+
+    def to_1hu(label, st, k0):
+        hist, times = [], []
+        for k in range(k0, max_iters):
+            times.append(timed(lambda: lalm.lalm_iterate(plan, y, w, denom, beta, delta, st, M, n_inner=n_inner)))
+            hist.append(round(rmsd(st.x, x_star), 3))
+            if (k + 1) % 5 == 0 or hist[-1] <= 1.0:
+                print("  %s iteration %d: %.3f HU" % (label, k + 1, hist[-1]), flush=True)
+            if hist[-1] <= 1.0:
+                break
+        return hist, times
+
+    plain_hist, plain_t = to_1hu("plain", zero(), 0)
+    # warm start
+    params = torch.as_tensor(np.load(weights), device=dev).contiguous()
+    net = lalm.lalm_unet_create(batch, ny, nx)
+    st2 = zero()
+    t_in = timed(lambda: lalm.lalm_iterate(plan, y, w, denom, beta, delta, st2, iters_in * M, n_inner=n_inner))
+    x_in = st2.x.clone()
+    xt = torch.empty_like(x_in)
+    hw = ny * nx
+
+    def network():
+        for z0 in range(0, nz, batch):
+            b = min(batch, nz - z0)
+            lalm.lalm_unet_forward(net, params, x_in[z0 * hw:(z0 + b) * hw], xt[z0 * hw:(z0 + b) * hw], b,
+                                   in_scale, True)
+
+    t_net = timed(network)
+    t1 = time.perf_counter()
+    psi_in, psi_net = cost(x_in), cost(xt)
+    t_guard = time.perf_counter() - t1
+    kept = psi_net < psi_in
+    rmsd_in, rmsd_net = rmsd(x_in, x_star), rmsd(xt, x_star)
+    print("  warm: %d iterations %.2f HU; network on %d slices %.3f s -> %.2f HU; guard %.3f s, Psi %.6e -> %.6e, "
+          "kept %s" % (iters_in, rmsd_in, nz, t_net, rmsd_net, t_guard, psi_in, psi_net, kept), flush=True)
+    if kept:
+        st2 = lalm.LalmState(xt.clone(), torch.zeros_like(xt), torch.zeros_like(xt))
+    del xt, x_in
+    wh, wt = to_1hu("warm", st2, iters_in)
+    warm_hist = wh
+    lalm.lalm_unet_destroy(net)
+
+    def reached(hist, times, k0, extra):
+        i = next((j for j, e in enumerate(hist) if e <= 1.0), None)
+        return (None, None) if i is None else (k0 + i + 1, round(extra + sum(times[:i + 1]), 3))
+
+    ip, sp = reached(plain_hist, plain_t, 0, 0.0)
+    iw, sw = reached(warm_hist, wt, iters_in, t_in + t_net + t_guard)
+    return dict(workload=name, M=M, n_inner=n_inner, iters_in=iters_in, max_iters=max_iters,
+                xstar=("OS-LALM-%d-c-%d for %d iterations, then one-subset OS-LALM-1-c-%d for %d iterations "
+                       "(last change over 10 iterations %.4f HU)" % (M, n_inner, warm_iters, n_inner, k, change)),
+                kept=bool(kept), psi_in=psi_in, psi_net=psi_net, rmsd_hu_in=round(rmsd_in, 3),
+                rmsd_hu_unet=round(rmsd_net, 3), unet_s=round(t_net, 4), guard_s=round(t_guard, 4),
+                plain=dict(iters_to_1hu=ip, wall_s_to_1hu=sp, rmsd_hu=plain_hist,
+                           s_per_iteration=round(float(np.median(plain_t)), 4)),
+                warm=dict(iters_to_1hu=iw, wall_s_to_1hu=sw, rmsd_hu_after_in=warm_hist))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="U-Net warm start for OS-LALM: pairs, training, evaluation")
     ap.add_argument("--workload", default="fan2d_512")
@@ -575,6 +764,12 @@ def main(argv=None):
                     help="inner FISTA iterations per subset step of the plain and warm-started runs")
     ap.add_argument("--volume", default=None,
                     help="3D workload: per-slice warm start with the committed weights (no training)")
+    ap.add_argument("--volume-train", type=int, default=0, metavar="K",
+                    help="with --volume: train on the slices of K synthetic scans of that workload, write --weights, "
+                         "then run to 1 HU on the workload's own scan with those weights")
+    ap.add_argument("--volume-eval", action="store_true",
+                    help="with --volume: run to 1 HU on the workload's own scan with --weights, plain against "
+                         "warm-started, both with --n-inner")
     ap.add_argument("--out", default=None, help="JSON summary path")
     ap.add_argument("--iters-target", type=int, default=None,
                     help="iterations behind a training target (default: the warm-start settings' value)")
@@ -586,6 +781,22 @@ def main(argv=None):
 
     import multiprocessing as mp
     import synth
+    if args.volume and (args.volume_train or args.volume_eval):
+        res = {}
+        if args.volume_train:
+            seeds = list(range(310000, 310000 + args.volume_train))
+            res["train"] = train_volume(args.volume, seeds, args.weights, n_inner=args.n_inner,
+                                        iters_target=args.iters_target or 30, epochs=args.epochs)
+        res["eval"] = eval_volume(args.volume, args.weights, n_inner=args.n_inner, max_iters=args.max_iters)
+        ev = res["eval"]
+        print(json.dumps({k: v for k, v in ev.items() if k not in ("plain", "warm")}), flush=True)
+        print(json.dumps({k: {a: b for a, b in ev[k].items() if a not in ("rmsd_hu", "rmsd_hu_after_in")}
+                          for k in ("plain", "warm")}), flush=True)
+        if args.out:
+            os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+            with open(args.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return res
     if args.volume:
         res = run_volume(args.volume, args.weights)
         print(json.dumps({k: v for k, v in res.items() if k != "methods"}), flush=True)
