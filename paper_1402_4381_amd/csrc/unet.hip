@@ -55,6 +55,7 @@ struct GemmArgs {
     const float *bias;
     int relu;
     bf16 *y;               // E_FWD output (channels N)
+    bf16 *pool;            // conv3x3_kernel E_FWD: also the 2x2 max pooling of y (nullptr: none)
     int yup;               // E_FWD: 1 = store at output phase ab of a 2x grid; 2 = all four
                            // phases in one GEMM, column n = phase * yc + channel
     int yc;                // E_FWD, yup = 2: output channels (and bias entries)
@@ -568,6 +569,30 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(GemmArgs g, int tiles_per_
                 const long long pix = ((long long)b * g.gH + y) * g.gW + x;
                 *reinterpret_cast<bf16x8 *>(g.y + pix * g.N + n) = *reinterpret_cast<const bf16x8 *>(Cs + r * LDC + cv);
             }
+            if (g.pool) {
+                // 2x2 max pooling of the tile (its rows and columns start even;
+                // H and W are even): the window in scan order, a later value
+                // taken only when larger, as pool_fwd_kernel does
+                const int Ho = g.gH / 2, Wo = g.gW / 2;
+                for (int sl = tid; sl < (TH / 2) * (CV_TW / 2) * (BN / 8); sl += 256) {
+                    const int cv = (sl % (BN / 8)) * 8, q = sl / (BN / 8);
+                    const int qy = q / (CV_TW / 2), qx = q % (CV_TW / 2);
+                    const int yo = ty0 / 2 + qy, xo = tx0 / 2 + qx, n = n0 + cv;
+                    if (yo >= Ho || xo >= Wo || n >= g.N) continue;
+                    const int r0 = 2 * qy * CV_TW + 2 * qx;
+                    bf16x8 m = *reinterpret_cast<const bf16x8 *>(Cs + r0 * LDC + cv);
+                    const int rr[3] = {r0 + 1, r0 + CV_TW, r0 + CV_TW + 1};
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(Cs + rr[k] * LDC + cv);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if ((float)v[i] > (float)m[i]) m[i] = v[i];
+                    }
+                    const long long po = ((long long)b * Ho + yo) * Wo + xo;
+                    *reinterpret_cast<bf16x8 *>(g.pool + po * g.N + n) = m;
+                }
+            }
         } else if (col < g.N) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -802,10 +827,13 @@ __global__ void __launch_bounds__(256) wgrad_kernel(GemmArgs g)
 // channels).  Tiles per block: up to 4, as long as the grid keeps about
 // 4096 blocks (16 per CU).
 template <int EPI>
-hipError_t conv3x3(const GemmArgs &g, hipStream_t st)
+hipError_t conv3x3(const GemmArgs &g, hipStream_t st, bool fused_pool = false)
 {
     const int cin = g.ac1 + g.ac2;
-    if (g.N > 32 || (cin != 32 && cin != 64)) return gemm<A_CONV, B_W, EPI>(g, 1, st);
+    if (g.N > 32 || (cin != 32 && cin != 64)) {
+        if (fused_pool) return hipErrorInvalidValue;   // only the patch kernel pools
+        return gemm<A_CONV, B_W, EPI>(g, 1, st);
+    }
     const int ntiles = g.gB * ((g.gH + 7) / 8) * ((g.gW + CV_TW - 1) / CV_TW);
     const int tpb = std::max(1, std::min(4, ntiles / 4096));
     const dim3 grd((ntiles + tpb - 1) / tpb, 1);
@@ -816,34 +844,79 @@ hipError_t conv3x3(const GemmArgs &g, hipStream_t st)
 
 // ------------------------------------------------------------ VALU kernels
 
-// first layer: 3x3 conv 1 -> 32 with ReLU, x FP32 [P] (images), out bf16 [P][32]
-__global__ void conv1_fwd_kernel(const float *x, float in_scale, const float *w, const float *bias, bf16 *out,
-                                 int B, int H, int W)
+// first layer: 3x3 conv 1 -> 32 with ReLU, x FP32 [P] (images), out bf16
+// [P][32].  On the matrix cores: 32 consecutive pixels x 32 output channels
+// are one 32x32x16 MFMA, K = the 9 taps (zero-padded to 16): lanes 0-31 give
+// taps 0-7 of their pixel, lanes 32-63 tap 8 and zeros; the B operand
+// (bfloat16 weights, channel lane % 32) is loaded once.  A wave takes
+// C1_G groups of 32 pixels and issues all their input loads first.  Inputs
+// in_scale * x and weights rounded to bfloat16, FP32 accumulation.  Each
+// 32 x 32 result goes through LDS so every pixel's 64 bytes are written by
+// two lanes together.
+constexpr int C1_G = 4;
+
+__global__ void __launch_bounds__(256) conv1_mfma_kernel(const float *x, float in_scale, const float *w,
+                                                         const float *bias, bf16 *out, int B, int H, int W)
 {
+    __shared__ __attribute__((aligned(16))) bf16 Cs[4][32 * 40];   // per wave: 32 pixels x 32 channels (+8)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long P = (long long)B * H * W;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    int b, y, xx;
-    pix_decode((int)p, H, W, b, y, xx);
-    float v[9];
+    const int c = lane & 31, kh = lane >> 5;
+    bf16x8 bw;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
-        float s = 0.0f;
-        if (yy >= 0 && yy < H && xq >= 0 && xq < W) s = (float)(bf16)(in_scale * x[((long long)b * H + yy) * W + xq]);
-        v[t] = s;
+    for (int j = 0; j < 8; ++j) {
+        const int t = 8 * kh + j;
+        bw[j] = (bf16)(t < 9 ? w[c * 9 + t] : 0.0f);
     }
-    bf16x8 o[4];
+    const float bv = bias[c];
+    const long long base = ((long long)blockIdx.x * 4 + wv) * (32 * C1_G);   // first pixel of this wave
+    if (base >= P) return;                                                  // whole waves only
+    bf16x8 a[C1_G];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
-        float a = 0.0f;
+    for (int gi = 0; gi < C1_G; ++gi) {
+        const long long p = base + 32 * gi + c;
+        a[gi] = zero8();
+        if (p < P) {
+            int b, y, xx;
+            pix_decode((int)p, H, W, b, y, xx);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) a = fmaf((float)(bf16)w[c * 9 + t], v[t], a);
-        a = fmaxf(a + bias[c], 0.0f);
-        o[c >> 3][c & 7] = (bf16)a;
+            for (int j = 0; j < 8; ++j) {
+                const int t = 8 * kh + j;
+                if (t < 9) {
+                    const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
+                    float v = 0.0f;
+                    if (yy >= 0 && yy < H && xq >= 0 && xq < W) v = in_scale * x[((long long)b * H + yy) * W + xq];
+                    a[gi][j] = (bf16)v;
+                }
+            }
+        }
     }
+    bf16 *cs = Cs[wv];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(out + p * 32 + q * 8) = o[q];
+    for (int gi = 0; gi < C1_G; ++gi) {
+        floatx16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[gi], bw, acc, 0, 0, 0);
+        // element q: pixel 8(q/4) + 4(lane/32) + q%4 of the group, channel lane % 32
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = 8 * (q >> 2) + 4 * kh + (q & 3);
+            cs[r * 40 + c] = (bf16)fmaxf(acc[q] + bv, 0.0f);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        // 32 pixels x 64 bytes: lane takes pixel lane/2, half lane%2 (two 16-byte chunks)
+        const int r = lane >> 1, h = lane & 1;
+        const long long p = base + 32 * gi + r;
+        if (p < P) {
+            bf16 *dst = out + p * 32 + 16 * h;
+            *reinterpret_cast<bf16x8 *>(dst) = *reinterpret_cast<const bf16x8 *>(cs + r * 40 + 16 * h);
+            *reinterpret_cast<bf16x8 *>(dst + 8) = *reinterpret_cast<const bf16x8 *>(cs + r * 40 + 16 * h + 8);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // reads done before the next group's writes
+    }
 }
 
 // gradient of the first layer's weights and biases over a chunk of pixels:
@@ -1258,7 +1331,7 @@ lalm_status ufail(lalm_status c, const std::string &m)
 
 // forward 3x3 conv (cin >= 32) at grid (B, h, w)
 hipError_t conv_fwd(lalm_unet *n, int L, const bf16 *x1, int c1, const bf16 *x2, int c2, bf16 *y, const float *params,
-                    int B, int h, int w, hipStream_t st)
+                    int B, int h, int w, hipStream_t st, bf16 *pool = nullptr)
 {
     GemmArgs g{};
     g.M = B * h * w;
@@ -1271,7 +1344,8 @@ hipError_t conv_fwd(lalm_unet *n, int L, const bf16 *x1, int c1, const bf16 *x2,
     g.bias = params + n->boff[L];
     g.relu = 1;
     g.y = y;
-    return conv3x3<E_FWD>(g, st);
+    g.pool = pool;
+    return conv3x3<E_FWD>(g, st, pool != nullptr);
 }
 
 hipError_t up_fwd(lalm_unet *n, int L, const bf16 *x, bf16 *y, const float *params, int B, int h, int w,
@@ -1439,11 +1513,10 @@ lalm_status run_forward(lalm_unet *n, const float *params, const float *x, float
     const long long P = (long long)B * H * W;
     lalm_status s = prep_weights(n, params, st);
     if (s != LALM_OK) return s;
-    hipLaunchKernelGGL(conv1_fwd_kernel, dim3(nblk(P)), dim3(256), 0, st, x, in_scale, params + n->woff[E1A],
-                       params + n->boff[E1A], n->e1a, B, H, W);
+    hipLaunchKernelGGL(conv1_mfma_kernel, dim3((unsigned)((P + 128 * C1_G - 1) / (128 * C1_G))), dim3(256), 0, st, x,
+                       in_scale, params + n->woff[E1A], params + n->boff[E1A], n->e1a, B, H, W);
     UCHK("unet e1a", hipGetLastError());
-    UCHK("unet e1b", conv_fwd(n, E1B, n->e1a, 32, nullptr, 0, n->e1b, params, B, H, W, st));
-    hipLaunchKernelGGL(pool_fwd_kernel, dim3(nblk(P / 4 * 32 / 8)), dim3(256), 0, st, n->e1b, n->p1, B, H, W, 32);
+    UCHK("unet e1b", conv_fwd(n, E1B, n->e1a, 32, nullptr, 0, n->e1b, params, B, H, W, st, n->p1));   // and p1
     UCHK("unet e2a", conv_fwd(n, E2A, n->p1, 32, nullptr, 0, n->e2a, params, B, H2, W2, st));
     UCHK("unet e2b", conv_fwd(n, E2B, n->e2a, 64, nullptr, 0, n->e2b, params, B, H2, W2, st));
     hipLaunchKernelGGL(pool_fwd_kernel, dim3(nblk(P / 16 * 64 / 8)), dim3(256), 0, st, n->e2b, n->p2, B, H2, W2, 64);
