@@ -357,7 +357,7 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_cache")
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("name,iters", [("cone_axial_512x64", "1 2 20"), ("cone_helical_512x256", "1")])
+@pytest.mark.parametrize("name,iters", [("cone_axial_512x64", "1 2 20"), ("cone_helical_512x256", "1 2")])
 def test_full_size_iterations_against_oracle(L, name, iters):
     """The full 3D workloads (512x512x64 axial: 984 views, 888 x 64
     detector; 512x512x256 helical: 6888 views over 7 turns; M = 12,
