@@ -9,9 +9,11 @@ within 30 iterations for the continuation.  This runs the same comparison on
 the synthetic 2D fan-beam workload with the library's own kernels:
 
 * x*: one-subset OS-LALM with continuation (convergent) run long; for a
-  volume, where that is out of reach, OS-LALM with continuation and
-  several inner FISTA iterations per step, run until its change over the
-  last 10 iterations is far below 1 HU;
+  volume, OS-LALM with the workload's subsets, continuation and several
+  inner FISTA iterations per step, run until its change over the last 10
+  iterations is far below 1 HU (an M-subset limit point: on the helical
+  volume it lies about 0.8 HU from the one-subset reference the benchmark
+  builds, which matters only for differences near 1 HU);
 * every method from x0 = 0 with the workload's subsets and bit-reversal
   order, RMSD to x* after every iteration;
 * acceleration of rho over rho = 1 at a level R: iterations rho = 1 needs to

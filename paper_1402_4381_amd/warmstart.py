@@ -418,11 +418,12 @@ def run_volume(name, weights, iters_in=2, iters_ref=150, inner_ref=10, max_iters
     """Run to 1 HU on a 3D workload, with the per-slice warm start.
 
     The reference is OS-LALM with continuation and inner_ref inner FISTA
-    iterations (Sec. IV-A) run for iters_ref iterations: a converged
-    one-subset run is out of reach at this size, and the inner iterations
-    cost little here beside the projections while they speed up the
-    regularizer part of each step, which dominates the denominator of a
-    26-neighbour 3D regularizer.  From x0 = 0 every method below runs until
+    iterations (Sec. IV-A) run for iters_ref iterations, an M-subset limit
+    point (on the helical volume about 0.8 HU from the one-subset reference
+    that eval_volume and the benchmark build); the inner iterations cost
+    little here beside the projections while they speed up the regularizer
+    part of each step, which dominates the denominator of a 26-neighbour 3D
+    regularizer.  From x0 = 0 every method below runs until
     its ROI RMS difference to the reference is at most 1 HU (or max_iters):
     plain OS-LALM (n = 1), the same with n in `inners`, and the warm start
     (iters_in plain iterations, the network trained on 2D slices applied to
