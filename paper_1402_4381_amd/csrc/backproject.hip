@@ -555,7 +555,9 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
 {
     const GeoK &K = A.k;
     __shared__ float tile[2][32][33];
+    __shared__ float nbr[34][35];          // x of this step over the tile and a one-pixel halo
     __shared__ double s_red[16];
+    __shared__ float s_rho1;
     {
         // image bi of the batch
         const long long bi = blockIdx.z, im = bi * A.bs.img;
@@ -588,37 +590,64 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
     const int bx = tl / A.tiles_y, by = tl - bx * A.tiles_y;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + 32 * ty;
-    const int i = bx * 32 + tx, j = by * 32 + ty;
+    const int i0 = bx * 32, j0 = by * 32;
+    const int i = i0 + tx, j = j0 + ty;
     const bool inside = i < K.nx && j < K.ny;
     const long long idx = (long long)j * K.nx + i;
     // the scalar record and the loads that do not depend on it go out
     // together, before its status is tested (threads outside the image read
-    // pixel 0)
+    // pixel 0; pixel indices are clamped into the image)
     const DevScalars s = *A.sc;
     const long long ldx = inside ? idx : 0;
     const float p0 = A.part[ldx], p1 = A.part2[ldx], Go = A.G[ldx], gv = A.g[ldx];
     const float dv = LAST ? 0.0f : A.denom[ldx];
-    // the neighbourhoods of both candidates for x: the record's choice is
-    // not known yet
-    const Nbr2d n0 = load_nbr2d(K, A.xs0, i, j);
-    const Nbr2d n1 = load_nbr2d(K, A.xs1, i, j);
+    // x at this pixel and at one pixel of the tile's halo (threads 0..131:
+    // the rows above and below, then the columns left and right), for both
+    // candidates: the record's choice is not known yet
+    const long long cdx = (long long)min(j, K.ny - 1) * K.nx + min(i, K.nx - 1);
+    const float c0 = A.xs0[cdx], c1 = A.xs1[cdx];
+    const bool halo = tid < 132;
+    const int hy = tid < 34 ? -1 : (tid < 68 ? 32 : (tid < 100 ? tid - 68 : tid - 100));
+    const int hx = tid < 34 ? tid - 1 : (tid < 68 ? tid - 35 : (tid < 100 ? -1 : 32));
+    float h0 = 0.0f, h1 = 0.0f;
+    if (halo) {
+        const long long hdx = (long long)min(max(j0 + hy, 0), K.ny - 1) * K.nx + min(max(i0 + hx, 0), K.nx - 1);
+        h0 = A.xs0[hdx];
+        h1 = A.xs1[hdx];
+    }
     // keeps the compiler from sinking those loads below the status test
     asm volatile("" ::: "memory");
     if (s.status) return;
-    Nbr2d nx;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) nx.v[t] = s.sel ? n1.v[t] : n0.v[t];
+    const bool sel = s.sel != 0;
+    nbr[ty + 1][tx + 1] = sel ? c1 : c0;
+    if (halo) nbr[hy + 1][hx + 1] = sel ? h1 : h0;
     const float rho = (float)s.rho;
     const bool two = A.continuation != 0;
+    // rho of the continuing candidate, once per block
+    if (!LAST && two && tid == 0) s_rho1 = (float)continuation_rho(s.l + 1, A.rho_min);
+    // the pointwise part while the neighbourhood is being staged
     double part = 0.0;
-    float v0 = 0.0f, v1 = 0.0f;
+    float Gn = 0.0f, gn = 0.0f;
     if (inside) {
-        const float Gn = A.scale * (p0 + p1);
+        Gn = A.scale * (p0 + p1);
         part = ((double)gv - (double)Gn) * ((double)Gn - (double)Go);
-        const float gn = fmaf(rho, Gn, gv) / (rho + 1.0f);
+        gn = fmaf(rho, Gn, gv) / (rho + 1.0f);
         A.G[idx] = Gn;
         A.g[idx] = gn;
-        const float rv = reg_grad_2d(K, nx, i, j, A.beta, A.inv_delta2);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = part;
+    __syncthreads();
+    Nbr2d nx;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) nx.v[t] = nbr[ty + t / 3][tx + t % 3];
+    float v0 = 0.0f, v1 = 0.0f;
+    if (inside) {
+        // a tile whose halo lies inside the image drops no neighbour
+        const bool interior = i0 >= 1 && j0 >= 1 && i0 + 33 <= K.nx && j0 + 33 <= K.ny;
+        const float rv = interior ? reg_grad_2d_inner(nx, A.beta, A.inv_delta2)
+                                  : reg_grad_2d(K, nx, i, j, A.beta, A.inv_delta2);
         const float xv = nx.v[4];
         if (A.xw) A.xw[idx] = xv;
         if (LAST) {
@@ -631,21 +660,12 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
             A.xo0[idx] = v0;
             A.XN0[n_idx] = v0;
             if (two) {
-                const float r1 = (float)continuation_rho(s.l + 1, A.rho_min);
-                v1 = x_update(xv, Gn, gn, rv, r1, alpha, dv, curv, A.nonneg);
+                v1 = x_update(xv, Gn, gn, rv, s_rho1, alpha, dv, curv, A.nonneg);
                 A.xo1[idx] = v1;
                 A.XN1[n_idx] = v1;
             }
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-    if ((tid & 63) == 0) s_red[tid >> 6] = part;
-    if (!LAST) {
-        tile[0][ty][tx] = v0;
-        tile[1][ty][tx] = v1;
-    }
-    __syncthreads();
     if (tid == 0) {
         double t = s_red[0];
 #pragma unroll
@@ -653,7 +673,10 @@ __global__ void __launch_bounds__(1024) step2d_kernel(Step2dArgs A)
         A.partials[bx + A.tiles_x * by] = t;
     }
     if (LAST) return;
-    const int it = bx * 32 + ty, jt = by * 32 + tx;
+    tile[0][ty][tx] = v0;
+    tile[1][ty][tx] = v1;
+    __syncthreads();
+    const int it = i0 + ty, jt = j0 + tx;
     if (it < K.nx && jt < K.ny) {
         const long long t_idx = (long long)it * K.ldT + jt + 2;
         A.XT0[t_idx] = tile[0][tx][ty];

@@ -167,10 +167,13 @@ __device__ inline double fixed_sum_wave(const double *v, long long n, int lane)
     return a;
 }
 
-// d psi / dt for the hyperbola potential: t / sqrt(1 + (t/delta)^2)
+// d psi / dt for the hyperbola potential: t / sqrt(1 + (t/delta)^2).  The
+// argument of the reciprocal square root is at least 1, so the hardware
+// instruction alone gives what rsqrtf gives (rsqrtf adds a rescaling for
+// denormal arguments around the same instruction).
 __device__ inline float dpsi(float t, float inv_delta2)
 {
-    return t * rsqrtf(fmaf(t * t, inv_delta2, 1.0f));
+    return t * __builtin_amdgcn_rsqf(fmaf(t * t, inv_delta2, 1.0f));
 }
 
 // grad R at voxel (i, j, k): beta sum_{n in N} kappa psi'(x_c - x_n)
@@ -243,6 +246,21 @@ __device__ inline float reg_grad_2d(const GeoK &K, const Nbr2d &n, int i, int j,
             const float t = fmaf(kap, dpsi(xc - n.v[3 * (dy + 1) + (dx + 1)], inv_delta2), s);
             s = in ? t : s;
         }
+    }
+    return beta * s;
+}
+// reg_grad_2d for a pixel whose eight neighbours all lie inside the image:
+// the same terms in the same order, without the bounds tests.
+__device__ inline float reg_grad_2d_inner(const Nbr2d &n, float beta, float inv_delta2)
+{
+    const float r2 = 0.70710678118654752f;
+    const float xc = n.v[4];
+    float s = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        if (t == 4) continue;
+        const float kap = (t == 0 || t == 2 || t == 6 || t == 8) ? r2 : 1.0f;
+        s = fmaf(kap, dpsi(xc - n.v[t], inv_delta2), s);
     }
     return beta * s;
 }
