@@ -269,9 +269,12 @@ hipError_t fp_dispatch(const lalm_plan *p, const FPArgs &a, int nseg, int mode, 
 
 // ---------------------------------------------------------------- x-update
 //
-// One thread per voxel of a 32x32 (x, y) tile of one z slice.  Writes the
-// caller's image (UPD_STEP), XN directly (x fastest) and XT through an LDS
-// transpose (y fastest), so every global store is coalesced.
+// One thread per pixel of a 32x32 (x, y) tile, for one z slice (2D and the
+// first of several inner iterations) or UPD_ZS consecutive slices (3D
+// launches that store the padded layouts).  Writes the caller's image
+// (UPD_STEP), XN directly (x fastest) and XT through an LDS transpose (y
+// fastest), so every global store is coalesced.
+constexpr int UPD_ZS = 2;
 struct UpdArgs {
     GeoK k;
     float *x;
@@ -288,19 +291,38 @@ struct UpdArgs {
     ContArgs cont;
     // first of several inner iterations: v and the next momentum point go here
     float *vout, *zout;
-    BatchStr bs;            // image b = blockIdx.z / nz
+    BatchStr bs;            // image b of the batch: tiles of slice groups b nzb ..
+    int nimg;               // images in the batch
 };
 
-template <bool IS3D, int MODE>
-__global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
+template <bool IS3D, int MODE, int ZS>
+__global__ void __launch_bounds__(1024, 8) update_kernel(UpdArgs A)
 {
+    // a thread takes ZS consecutive slices of its (x, y) pixel and issues the
+    // loads of all of them before any arithmetic, so a wave keeps ZS times
+    // the bytes of one voxel's five loads in flight
     const GeoK &K = A.k;
-    __shared__ float tile[32][33];
+    __shared__ float tile[ZS][32][33];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int k = (int)(blockIdx.z % (unsigned)K.nz);
+    const unsigned nzb = (unsigned)(K.nz + ZS - 1) / ZS;      // slice groups per image
+    // tile of this block, in (x, y, slice group, image) order.  A launch
+    // that stores the padded layouts: the hardware hands consecutive blocks
+    // to the eight XCDs in turn, and XCD c takes the c-th eighth of the
+    // tiles, so the tiles beside a tile, whose stores complete the cache
+    // lines that its row segments of those layouts begin or end in, mostly
+    // store through the same L2.  The first of several inner iterations
+    // (vout) stores no layout and keeps the round-robin order, in which the
+    // XCDs work on neighbouring tiles and share the Infinity Cache, and one
+    // slice per thread (both measured faster there).  The grid is padded to
+    // a multiple of 8; padding blocks have no tile.
+    const unsigned ntx = (unsigned)(K.nx + 31) / 32, nty = (unsigned)(K.ny + 31) / 32;
+    const unsigned tl = A.vout ? blockIdx.x : (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    if (tl >= ntx * nty * nzb * A.nimg) return;
+    const unsigned bxt = tl % ntx, byt = (tl / ntx) % nty, bzt = tl / (ntx * nty);
+    const int k0 = (int)(bzt % nzb) * ZS;
     {
         // image bi of the batch
-        const long long bi = blockIdx.z / (unsigned)K.nz;
+        const long long bi = bzt / nzb;
         if (A.x) A.x += bi * A.bs.img;
         if (A.G) A.G += bi * A.bs.img;
         if (A.g) A.g += bi * A.bs.img;
@@ -315,21 +337,29 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         if (A.vout) A.vout += bi * A.bs.img;
         if (A.zout) A.zout += bi * A.bs.img;
     }
-    const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + ty;
-    const bool inside = i < K.nx && j < K.ny;
-    const long long idx = ((long long)k * K.ny + j) * K.nx + i;
+    const int i = (int)bxt * 32 + tx, j = (int)byt * 32 + ty;
+    const long long plane = (long long)K.nx * K.ny;
+    const long long idx0 = ((long long)k0 * K.ny + j) * K.nx + i;
+    bool in[ZS];
+#pragma unroll
+    for (int z = 0; z < ZS; ++z) in[z] = i < K.nx && j < K.ny && k0 + z < K.nz;
     // operands first: their loads overlap the continuation decision below
-    float v = 0.0f, Gv = 0.0f, gv = 0.0f, rv = 0.0f, dv = 0.0f;
-    if (inside) {
-        if (MODE == UPD_ONES) {
-            v = 1.0f;
-        } else {
-            v = A.x[idx];
-            if (MODE == UPD_STEP) {
-                Gv = A.G[idx];
-                gv = A.g[idx];
-                rv = A.gradR[idx];
-                dv = A.denom[idx];
+    float v[ZS], Gv[ZS], gv[ZS], rv[ZS], dv[ZS];
+#pragma unroll
+    for (int z = 0; z < ZS; ++z) {
+        v[z] = Gv[z] = gv[z] = rv[z] = dv[z] = 0.0f;
+        if (in[z]) {
+            const long long idx = idx0 + z * plane;
+            if (MODE == UPD_ONES) {
+                v[z] = 1.0f;
+            } else {
+                v[z] = A.x[idx];
+                if (MODE == UPD_STEP) {
+                    Gv[z] = A.G[idx];
+                    gv[z] = A.g[idx];
+                    rv[z] = A.gradR[idx];
+                    dv[z] = A.denom[idx];
+                }
             }
         }
     }
@@ -338,7 +368,7 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         if (A.do_finalize) {
             // every wave takes the same decision from the same fixed-order
             // sum; the first thread records it in the other scalar record
-            const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && k == 0 && tx == 0 && ty == 0;
+            const bool lead = bxt == 0 && byt == 0 && k0 == 0 && tx == 0 && ty == 0;
             if (!s.status) {
                 const double xi = fixed_sum_wave(A.partials, A.nblocks, (tx + 32 * ty) & 63);
                 s = continuation_update(s, A.cont, xi, false, lead);
@@ -347,30 +377,42 @@ __global__ void __launch_bounds__(1024) update_kernel(UpdArgs A)
         }
         if (s.status) return;
         const float rho = (float)s.rho;
-        if (inside) {
-            v = x_update(v, Gv, gv, rv, rho, (float)s.alpha, dv, A.beta * reg_curv_sum(K, i, j, k), A.nonneg);
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) {
+            if (!in[z]) continue;
+            const long long idx = idx0 + z * plane;
+            v[z] = x_update(v[z], Gv[z], gv[z], rv[z], rho, (float)s.alpha, dv[z],
+                            A.beta * reg_curv_sum(K, i, j, k0 + z), A.nonneg);
             if (A.vout) {
-                A.vout[idx] = v;                  // first FISTA momentum is zero: z = v
-                A.zout[idx] = v;
+                A.vout[idx] = v[z];               // first FISTA momentum is zero: z = v
+                A.zout[idx] = v[z];
             } else {
-                A.x[idx] = v;
+                A.x[idx] = v[z];
             }
         }
         if (A.vout) return;                       // the projector layouts follow the last inner iteration
     }
-    if (inside) {
-        const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
-                                     : ((long long)j * K.ldN + i + 2);
-        A.XN[n_idx] = v;
+#pragma unroll
+    for (int z = 0; z < ZS; ++z) {
+        const int k = k0 + z;
+        if (in[z]) {
+            const long long n_idx = IS3D ? ((long long)j * K.slabN + (long long)(k + 2) * K.ldN + i + 2)
+                                         : ((long long)j * K.ldN + i + 2);
+            A.XN[n_idx] = v[z];
+        }
+        tile[z][ty][tx] = v[z];
     }
-    tile[ty][tx] = v;
     __syncthreads();
     {
-        const int it = blockIdx.x * 32 + ty, jt = blockIdx.y * 32 + tx;
-        if (it < K.nx && jt < K.ny) {
-            const long long t_idx = IS3D ? ((long long)it * K.slabT + (long long)(k + 2) * K.ldT + jt + 2)
-                                         : ((long long)it * K.ldT + jt + 2);
-            A.XT[t_idx] = tile[tx][ty];
+        const int it = (int)bxt * 32 + ty, jt = (int)byt * 32 + tx;
+#pragma unroll
+        for (int z = 0; z < ZS; ++z) {
+            const int k = k0 + z;
+            if (it < K.nx && jt < K.ny && k < K.nz) {
+                const long long t_idx = IS3D ? ((long long)it * K.slabT + (long long)(k + 2) * K.ldT + jt + 2)
+                                             : ((long long)it * K.ldT + jt + 2);
+                A.XT[t_idx] = tile[z][tx][ty];
+            }
         }
     }
 }
@@ -457,10 +499,15 @@ __global__ void __launch_bounds__(1024) inner_kernel(InnerArgs A)
 template <bool IS3D>
 hipError_t upd_dispatch(const lalm_plan *p, const UpdArgs &a, int mode, hipStream_t st)
 {
-    dim3 blk(32, 32), grd((a.k.nx + 31) / 32, (a.k.ny + 31) / 32, (unsigned)(a.k.nz * p->B));
-    if (mode == UPD_LAYOUT) return klaunch(p, update_kernel<IS3D, UPD_LAYOUT>, grd, blk, st, a);
-    if (mode == UPD_ONES) return klaunch(p, update_kernel<IS3D, UPD_ONES>, grd, blk, st, a);
-    return klaunch(p, update_kernel<IS3D, UPD_STEP>, grd, blk, st, a);
+    const int zs = (IS3D && !a.vout) ? UPD_ZS : 1;
+    const long long ntile = (long long)((a.k.nx + 31) / 32) * ((a.k.ny + 31) / 32) * ((a.k.nz + zs - 1) / zs) * p->B;
+    if (ntile > 0x7FFFFFF8LL) return hipErrorInvalidValue;
+    dim3 blk(32, 32), grd((unsigned)((ntile + 7) / 8 * 8));   // padded to the eight XCDs
+    constexpr int ZL = IS3D ? UPD_ZS : 1;                        // launches that store the layouts
+    if (mode == UPD_LAYOUT) return klaunch(p, update_kernel<IS3D, UPD_LAYOUT, ZL>, grd, blk, st, a);
+    if (mode == UPD_ONES) return klaunch(p, update_kernel<IS3D, UPD_ONES, ZL>, grd, blk, st, a);
+    if (a.vout) return klaunch(p, update_kernel<IS3D, UPD_STEP, 1>, grd, blk, st, a);
+    return klaunch(p, update_kernel<IS3D, UPD_STEP, ZL>, grd, blk, st, a);
 }
 
 __global__ void set_scalars_kernel(DevScalars *sc, long long l, double rho, long long step, double alpha)
@@ -642,6 +689,7 @@ hipError_t launch_update(const lalm_plan *p, int mode, float *x, const float *G,
     a.vout = mode == UPD_STEP ? vout : nullptr;
     a.zout = mode == UPD_STEP ? zout : nullptr;
     a.bs = batch_str(p);
+    a.nimg = p->B;
     hipError_t e = p->is3d ? upd_dispatch<true>(p, a, mode, st) : upd_dispatch<false>(p, a, mode, st);
     if (a.do_finalize) p->sc_cur ^= 1;
     return e;
