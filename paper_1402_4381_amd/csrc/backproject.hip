@@ -141,6 +141,10 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
     // (the plan keeps a subset's residual below 4 GiB)
     const char *rbase = (const char *)A.r;
     const unsigned nb4 = 4u * (unsigned)K.nb;
+    // the gathered row pair of a slice: r0 in [0, nr - 2] and r0 + 1 (with a
+    // single detector row, row 0 twice; s_row[1] is then a padding row)
+    const float r0_max = (float)max(K.nr - 2, 0);
+    const unsigned row_step = K.nr > 1 ? nb4 : 0u;
     // helical subsets: z0 never decreases along the slots, so the views that
     // can reach the block's slices form one range, found by two binary
     // searches.  The bound uses tmax <= dso + |block centre| + bhd, so every
@@ -212,28 +216,33 @@ __global__ void __launch_bounds__(256) bp_kernel(BPArgs A)
                     for (int t = 0; t < KZ; ++t) {
                         const int k = kb + t;
                         const float zk = V.z0 - (float)k;   // zeta - k = v_r qz + zk
-                        // r0 <= nr: rows r0, r0 + 1 exist in s_row
-                        const int r0 = min(max(0, (int)ceilf(fmaf(-zk, inv, c_lo))), K.nr);
+                        // first row r0 of the window, clamped to [0, nr - 2]
+                        // so that r0 and r0 + 1 are detector rows: a row below
+                        // the window's own first row lies at or beyond slice
+                        // k - 1 and has weight exactly zero, so when the clamp
+                        // moves r0 down the pair still sums the same terms
+                        const int r0 = (int)__builtin_amdgcn_fmed3f(ceilf(fmaf(-zk, inv, c_lo)), 0.0f, r0_max);
                         const int r1 = min(K.nr - 1, (int)floorf(fmaf(-zk, inv, c_hi)));
                         // Rows r0..r1 of the window.  The linear-interpolation
                         // weight of a row at slice coordinate zeta on slice k is
                         // the tent 1 - |zeta - k| clipped at 0.  The first
                         // BP3_RW rows go without branches: weights first, their
-                        // residual gathers issued together (the gather row is
-                        // clamped; rows past r1 lie at or beyond slice k + 1, or
-                        // are padding, so their weight is zero and they add an
+                        // residual gathers issued together (a row of the pair
+                        // outside the window lies beyond slice k -+ 1, or is a
+                        // padding row, so its weight is zero and it adds an
                         // exact zero).  Row offsets: rows < 256 and 4 x channels
                         // < 2^24, so a full-rate 24-bit multiply-add.  The rows'
                         // weighted residuals are summed in row order, then
                         // scaled by the in-plane weight once.
+                        static_assert(BP3_RW == 2, "the clamp of r0 keeps a pair of rows on the detector");
                         float wz[BP3_RW], rr[BP3_RW];
+                        const unsigned g0 = (unsigned)__umul24((unsigned)r0, nb4) + cb;
 #pragma unroll
                         for (int u = 0; u < BP3_RW; ++u) {
                             const float2 rowq = s_row[r0 + u];
-                            const int rw = min(r0 + u, K.nr - 1);
                             const float w = fmaxf(0.0f, 1.0f - fabsf(fmaf(rowq.x, qz, zk)));
                             wz[u] = SCALED ? w : w * rowq.y;
-                            rr[u] = *(const float *)(rbase + ((unsigned)__umul24((unsigned)rw, nb4) + cb));
+                            rr[u] = *(const float *)(rbase + (g0 + (unsigned)u * row_step));
                         }
                         float sum = wz[0] * rr[0];
 #pragma unroll
