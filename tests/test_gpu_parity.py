@@ -59,6 +59,11 @@ CASES = [
     ("fan2d_128", RAGGED2D, 7),             # ragged tiles, ragged subsets
     ("cone_axial_512x64", MED3D, 5),
     ("cone_helical_512x256", MEDHEL, 6),
+    # detectors of one and two rows: the cone back-projector's gathered row
+    # pair then starts at row 0 (one row: row 0 twice, the second weighed by a
+    # padding row)
+    ("tiny3d", {"n_rows": 1}, 2),
+    ("tiny3d", {"n_rows": 2}, 2),
 ]
 
 
